@@ -1,0 +1,197 @@
+/*
+ * elh.h -- C ABI of the MI355X library for the matrix-free elastic
+ * Helmholtz multigrid solver of Yovel & Treister, "LFA-tuned matrix-free
+ * multigrid method for the elastic Helmholtz equation".
+ *
+ * Problem (Section 2.2, eq. linsys; Section 3.1, eq. mixed-discretized):
+ * solve  H^beta u = q  where H^beta is the beta-spread MAC discretisation
+ * of the mixed displacement/pressure elastic Helmholtz system (eq.
+ * elasticMixed) with heterogeneous lam, mu, rho and attenuation gamma.
+ * The preconditioner is a multigrid cycle (Algorithm 1, applied
+ * recursively) on the shifted operator H^beta_s (gamma -> gamma + alpha,
+ * Section 2.2, eq. shift), used on the right of restarted flexible GMRES
+ * (Section 5: FGMRES(5), zero initial guess, relative-residual stop).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Pointers: unless stated otherwise every array pointer is a DEVICE
+ *   pointer on the GPU the handle was created on; host pointers are marked
+ *   "(host)".  The caller owns all buffers it passes; the handle owns its
+ *   media copies, hierarchy and workspaces.
+ * Grid: n[0..2] = cells along x_1, x_2, x_3 (n[2] = 1 in 2D); spacing h.
+ * Media (lam, mu, rho): real float64 arrays of n[dim-1]*...*n[0] cells,
+ *   C order with x_1 fastest (numpy shape (n_d, ..., n_1)).
+ * Vectors: complex, interleaved (re, im), float64 (ELH_C128) or float32
+ *   (ELH_C64).  One vector = d+1 fields u_1..u_d, p, each of n cells in the
+ *   media order; a batch of nrhs vectors is contiguous:
+ *   (nrhs, d+1, n_d, ..., n_1).  Field u_k lives on the faces normal to
+ *   x_k (MAC grid, Section 2.3, Figure 1a): its entry with index i along
+ *   x_k is the face between cells i-1 and i, so index 0 is the domain
+ *   boundary face.  Boundary faces are not unknowns: they are ignored on
+ *   input and written as 0 on output.
+ * Levels: level 0 is the finest; level l has n/2^l cells and spacing
+ *   2^l h; coarse media are the means of the 2^d child cells.
+ * Streams: all work is enqueued on the stream given to elh_create; calls
+ *   returning vectors are asynchronous except elh_solve* (which wait for
+ *   their statistics).  Calls on one handle must not overlap.
+ * Errors: 0 = success; ELH_NOT_CONVERGED (> 0) still writes the best
+ *   iterate and statistics; negative codes leave outputs unspecified.
+ *   elh_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef ELH_H
+#define ELH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ELH_OK = 0,
+  ELH_NOT_CONVERGED = 1,
+  ELH_ERR_ARG = -1,      /* invalid argument (sizes, pointers, parameters)  */
+  ELH_ERR_HIP = -2,      /* a HIP runtime call failed                        */
+  ELH_ERR_NUMERIC = -3,  /* NaN/Inf in a norm, or a Krylov breakdown         */
+  ELH_ERR_OOM = -4,      /* device allocation failed                         */
+  ELH_ERR_STATE = -5     /* handle not usable (e.g. setup failed)            */
+} elh_status;
+
+typedef enum { ELH_C64 = 1, ELH_C128 = 2 } elh_dtype;
+
+/* elh_apply / elh_residual / elh_relax / elh_vcycle flags */
+enum { ELH_SHIFTED = 1,  /* use H^beta_s (alpha added to gamma), eq. shift */
+       ELH_ADJOINT = 2   /* use the conjugate transpose                     */ };
+
+/* coarsest-level solver (Section 3.2, "Coarsest grid solution") */
+enum { ELH_COARSE_KRYLOV = 0,  /* restarted GMRES preconditioned by red-black
+                                  Vanka sweeps, fixed budget / residual drop */
+       ELH_COARSE_DENSE = 1,   /* exact solve (dense inverse built at setup;
+                                  the paper's LU choice for 2D)             */
+       ELH_COARSE_RELAX = 2    /* fixed number of red-black Vanka sweeps    */ };
+
+typedef struct {
+  int dim;              /* 2 or 3                                              */
+  int n[3];             /* cells along x_1, x_2, x_3; each divisible by
+                           2^(levels-1)                                       */
+  double h;             /* grid spacing of level 0                            */
+  double omega;         /* angular frequency (eq. elasticHelm)                */
+  double gamma;         /* physical attenuation (eq. elasticHelm)             */
+  double alpha;         /* preconditioner shift added to gamma (eq. shift)    */
+  double beta;          /* spread weight of the compact stencils, (0,1];
+                           2/3 is the LFA-tuned value (Section 4.3)           */
+  double abl_width;     /* absorbing-layer width, PHYSICAL units (0 = none)   */
+  double abl_amp;       /* absorbing-layer peak attenuation: the layer adds
+                           abl_amp * sum_k (delta_k/abl_width)^2 to gamma,
+                           delta_k = distance into the layer along x_k        */
+  int levels;           /* multigrid levels, 1..8 (1 = coarsest solve only)   */
+  int nu1, nu2;         /* pre/post red-black Vanka sweeps (Section 3.2)      */
+  double damping[8];    /* Vanka damping w per level (Section 5.2)            */
+  int coarse_mode;      /* ELH_COARSE_*                                       */
+  int coarse_sweeps;    /* Vanka sweeps per coarse relaxation/preconditioning */
+  int coarse_restart;   /* inner GMRES restart length (KRYLOV)                */
+  int coarse_maxit;     /* inner GMRES iterations budget (KRYLOV)             */
+  double coarse_rtol;   /* inner residual-drop stop, 0 = always full budget   */
+  double coarse_damping;/* Vanka damping on the coarsest level (<=0: use
+                           damping[levels-1])                                 */
+  int precond_dtype;    /* ELH_C128: float64 cycle; ELH_C64: float32 cycle
+                           inside the float64 Krylov solve (Section 5.3)      */
+} elh_desc;
+
+typedef struct {
+  int restart;          /* FGMRES restart length m (paper: 5)                 */
+  int maxit;            /* maximum preconditioner applications                */
+  double rtol;          /* stop at ||q - H u|| <= rtol ||q|| (per RHS)        */
+} elh_solve_opts;
+
+typedef struct {        /* (host) one record per right-hand side              */
+  int iters;            /* preconditioner applications (Section 5 counts)     */
+  int restarts;
+  int status;           /* ELH_OK / ELH_NOT_CONVERGED / ELH_ERR_NUMERIC       */
+  double relres;        /* final true relative residual, float64              */
+} elh_solve_stats;
+
+typedef struct elh_handle elh_handle;
+
+/* Create a handle: copies the media (device float64 arrays), builds the
+ * coarse hierarchy (media means, kappa = 1/(lam+mu), float32 copies) and,
+ * for ELH_COARSE_DENSE, the coarsest-level inverse.  stream: hipStream_t
+ * (NULL = default stream).  Section 3.1 (operator), Section 3.2 (hierarchy
+ * by re-discretisation). */
+int elh_create(const elh_desc* desc, const double* lam, const double* mu,
+               const double* rho, void* stream, elh_handle** out);
+
+/* Replace the media of an existing handle (same sizes); rebuilds the
+ * hierarchy in place without reallocating. */
+int elh_set_media(elh_handle* h, const double* lam, const double* mu,
+                  const double* rho);
+
+int elh_destroy(elh_handle* h);
+
+/* y = H x on `level` (eq. mixed-discretized; ELH_SHIFTED: H_s; ELH_ADJOINT:
+ * H^H).  x and y: nrhs vectors of that level, dtype `dtype`; x != y. */
+int elh_apply(elh_handle* h, int level, int flags, int dtype, int nrhs,
+              const void* x, void* y);
+
+/* r = b - H x  (same operator selection as elh_apply); r may alias b. */
+int elh_residual(elh_handle* h, int level, int flags, int dtype, int nrhs,
+                 const void* b, const void* x, void* r);
+
+/* rc = R (b - H_s x): residual of the shifted operator on `level` followed
+ * by the MAC restriction of Section 2.3 (eqs. pIntergrid, u2Intergrid and
+ * their 3D tensor-product form) to level+1.  x == NULL means x = 0.
+ * flags: ELH_ADJOINT selects H_s^H. */
+int elh_restrict_residual(elh_handle* h, int level, int flags, int dtype,
+                          int nrhs, const void* b, const void* x, void* rc);
+
+/* x += P e: MAC prolongation (Section 2.3) from level+1 to `level`. */
+int elh_prolong_add(elh_handle* h, int level, int dtype, int nrhs,
+                    const void* e, void* x);
+
+/* One colour of red-black full-Vanka relaxation of H_s x = b on `level`
+ * (Section 2.3 Vanka smoother, Section 3.2 red-black order): with the
+ * residual r = b - H_s x, every cell of colour `colour` ((i_1+..+i_d) mod
+ * 2) solves its (2d+1)x(2d+1) block (its unknown faces and its pressure)
+ * and adds w * correction; w = damping[level] (coarse_damping on the
+ * coarsest level).  x is updated in place.  flags: ELH_ADJOINT. */
+int elh_relax(elh_handle* h, int level, int flags, int dtype, int nrhs,
+              int colour, const void* b, void* x);
+
+/* x = coarsest-level solve of H_s x = b (mode desc->coarse_mode) on level
+ * levels-1. */
+int elh_coarse_solve(elh_handle* h, int flags, int dtype, int nrhs,
+                     const void* b, void* x);
+
+/* x = V(nu1,nu2)-cycle approximation of H_s^{-1} b on level 0 from a zero
+ * initial guess (Algorithm 1 with one recursive call).  flags:
+ * ELH_ADJOINT for the cycle on H_s^H. */
+int elh_vcycle(elh_handle* h, int flags, int dtype, int nrhs, const void* b,
+               void* x);
+
+/* Solve H u = q for nrhs right-hand sides (float64 q, u on level 0) by
+ * FGMRES(opts->restart) right-preconditioned with the cycle in
+ * desc->precond_dtype.  u is overwritten (zero initial guess).  stats:
+ * (host) array of nrhs records, may be NULL. */
+int elh_solve(elh_handle* h, int nrhs, const void* q, void* u,
+              const elh_solve_opts* opts, elh_solve_stats* stats);
+
+/* Same for the adjoint system H^H v = r (preconditioned by the cycle on
+ * H_s^H). */
+int elh_solve_adjoint(elh_handle* h, int nrhs, const void* r, void* v,
+                      const elh_solve_opts* opts, elh_solve_stats* stats);
+
+/* Parameter gradient of an FWI misfit by the adjoint state:
+ *   g_m(c) = - Re sum_s v_s^H (dH/dm_c) u_s,  m in {lam, mu, rho},
+ * for forward fields u and adjoint fields v (float64, nrhs each, level 0).
+ * g_lam, g_mu, g_rho: float64 arrays of n cells (overwritten). */
+int elh_gradient(elh_handle* h, int nrhs, const void* u, const void* v,
+                 double* g_lam, double* g_mu, double* g_rho);
+
+/* Number of levels, cells per axis (x-order) and spacing of `level`. */
+int elh_level_info(elh_handle* h, int level, int* n3, double* hl);
+
+const char* elh_status_string(int status);
+const char* elh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ELH_H */

@@ -1,0 +1,194 @@
+"""Python binding of libelh: argument marshalling only.
+
+Every numerical step runs in the HIP library; torch supplies device memory
+and the current stream.  Vectors are torch complex tensors on the GPU with
+shape (d+1, n_d, ..., n_1) or (nrhs, d+1, n_d, ..., n_1) (fields u_1..u_d,
+p; x_1 fastest; index 0 of u_k along x_k is the boundary face, held at 0).
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dtype_code(t):
+    if t.dtype == torch.complex128:
+        return L.ELH_C128
+    if t.dtype == torch.complex64:
+        return L.ELH_C64
+    raise TypeError("vectors must be complex64 or complex128, got %s" % t.dtype)
+
+
+class Problem:
+    """One elastic Helmholtz problem (media + discretisation + solver
+    parameters) living on one GPU.
+
+    lam, mu, rho: float64 tensors of numpy shape (n_d, ..., n_1), any
+    device (copied to the current GPU).  Lengths (h, abl_width) are in
+    physical units.
+    """
+
+    def __init__(self, lam, mu, rho, h=1.0, omega=1.0, gamma=0.01, alpha=0.3,
+                 beta=2.0 / 3.0, abl_width=0.0, abl_amp=2.0, levels=3, nu1=1,
+                 nu2=1, damping=(0.55, 0.35, 0.25), coarse_mode="krylov",
+                 coarse_sweeps=2, coarse_restart=5, coarse_maxit=10,
+                 coarse_rtol=0.0, coarse_damping=0.0, precond_dtype=torch.complex128,
+                 device=None):
+        self.lib = L.load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        lam = torch.as_tensor(lam, dtype=torch.float64).to(self.device).contiguous()
+        mu = torch.as_tensor(mu, dtype=torch.float64).to(self.device).contiguous()
+        rho = torch.as_tensor(rho, dtype=torch.float64).to(self.device).contiguous()
+        if not (lam.shape == mu.shape == rho.shape):
+            raise ValueError("lam, mu, rho must have the same shape")
+        self.shape = tuple(lam.shape)
+        self.dim = len(self.shape)
+        if self.dim not in (2, 3):
+            raise ValueError("media must be 2D or 3D")
+        d = L.Desc()
+        d.dim = self.dim
+        n = list(reversed(self.shape)) + [1] * (3 - self.dim)
+        for a in range(3):
+            d.n[a] = n[a]
+        d.h, d.omega, d.gamma, d.alpha, d.beta = h, omega, gamma, alpha, beta
+        d.abl_width, d.abl_amp = abl_width, abl_amp
+        d.levels, d.nu1, d.nu2 = levels, nu1, nu2
+        damping = list(damping)
+        while len(damping) < 8:
+            damping.append(damping[-1])
+        for i in range(8):
+            d.damping[i] = damping[i]
+        modes = {"krylov": L.ELH_COARSE_KRYLOV, "dense": L.ELH_COARSE_DENSE, "relax": L.ELH_COARSE_RELAX}
+        d.coarse_mode = modes[coarse_mode]
+        d.coarse_sweeps, d.coarse_restart, d.coarse_maxit = coarse_sweeps, coarse_restart, coarse_maxit
+        d.coarse_rtol, d.coarse_damping = coarse_rtol, coarse_damping
+        d.precond_dtype = L.ELH_C64 if precond_dtype == torch.complex64 else L.ELH_C128
+        self.desc = d
+        self.levels = levels
+        self._media = (lam, mu, rho)
+        self.handle = ctypes.c_void_p(0)
+        with torch.cuda.device(self.device):
+            st = torch.cuda.current_stream(self.device).cuda_stream
+            L.check(self.lib.elh_create(ctypes.byref(d), _ptr(lam), _ptr(mu), _ptr(rho),
+                                        ctypes.c_void_p(st), ctypes.byref(self.handle)))
+
+    # -- housekeeping ---------------------------------------------------------
+    def close(self):
+        if self.handle and self.handle.value:
+            self.lib.elh_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_media(self, lam, mu, rho):
+        lam = torch.as_tensor(lam, dtype=torch.float64).to(self.device).contiguous()
+        mu = torch.as_tensor(mu, dtype=torch.float64).to(self.device).contiguous()
+        rho = torch.as_tensor(rho, dtype=torch.float64).to(self.device).contiguous()
+        L.check(self.lib.elh_set_media(self.handle, _ptr(lam), _ptr(mu), _ptr(rho)))
+        self._media = (lam, mu, rho)
+
+    def level_shape(self, level):
+        n3 = (ctypes.c_int * 3)()
+        hl = ctypes.c_double()
+        L.check(self.lib.elh_level_info(self.handle, level, n3, ctypes.byref(hl)))
+        return tuple(reversed([n3[a] for a in range(self.dim)])), hl.value
+
+    def _vec(self, t, level):
+        shp, _ = self.level_shape(level)
+        if not t.is_cuda or t.device != self.device:
+            raise ValueError("vectors must live on %s" % self.device)
+        if not t.is_contiguous():
+            raise ValueError("vectors must be contiguous")
+        full = (self.dim + 1,) + shp
+        if tuple(t.shape) == full:
+            return 1
+        if t.dim() == len(full) + 1 and tuple(t.shape[1:]) == full:
+            return t.shape[0]
+        raise ValueError("vector shape %s does not match level %d layout %s" % (tuple(t.shape), level, full))
+
+    @staticmethod
+    def _flags(shifted, adjoint):
+        return (L.ELH_SHIFTED if shifted else 0) | (L.ELH_ADJOINT if adjoint else 0)
+
+    # -- level operations -----------------------------------------------------
+    def apply(self, x, level=0, shifted=False, adjoint=False, out=None):
+        nrhs = self._vec(x, level)
+        y = torch.empty_like(x) if out is None else out
+        L.check(self.lib.elh_apply(self.handle, level, self._flags(shifted, adjoint), _dtype_code(x), nrhs,
+                                   _ptr(x), _ptr(y)))
+        return y
+
+    def residual(self, b, x, level=0, shifted=False, adjoint=False):
+        nrhs = self._vec(x, level)
+        r = torch.empty_like(x)
+        L.check(self.lib.elh_residual(self.handle, level, self._flags(shifted, adjoint), _dtype_code(x), nrhs,
+                                      _ptr(b), _ptr(x), _ptr(r)))
+        return r
+
+    def restrict_residual(self, b, x=None, level=0, adjoint=False):
+        nrhs = self._vec(b, level)
+        cshape, _ = self.level_shape(level + 1)
+        full = (self.dim + 1,) + cshape
+        out = torch.empty(((nrhs,) if b.dim() == len(full) + 1 else ()) + full, dtype=b.dtype, device=b.device)
+        L.check(self.lib.elh_restrict_residual(self.handle, level, self._flags(False, adjoint), _dtype_code(b),
+                                               nrhs, _ptr(b), _ptr(x), _ptr(out)))
+        return out
+
+    def prolong_add(self, e, x, level=0):
+        nrhs = self._vec(x, level)
+        L.check(self.lib.elh_prolong_add(self.handle, level, _dtype_code(x), nrhs, _ptr(e), _ptr(x)))
+        return x
+
+    def relax(self, b, x, colour, level=0, adjoint=False):
+        nrhs = self._vec(x, level)
+        L.check(self.lib.elh_relax(self.handle, level, self._flags(False, adjoint), _dtype_code(x), nrhs,
+                                   colour, _ptr(b), _ptr(x)))
+        return x
+
+    def coarse_solve(self, b, adjoint=False):
+        nrhs = self._vec(b, self.levels - 1)
+        x = torch.empty_like(b)
+        L.check(self.lib.elh_coarse_solve(self.handle, self._flags(False, adjoint), _dtype_code(b), nrhs,
+                                          _ptr(b), _ptr(x)))
+        return x
+
+    def vcycle(self, b, adjoint=False):
+        nrhs = self._vec(b, 0)
+        x = torch.empty_like(b)
+        L.check(self.lib.elh_vcycle(self.handle, self._flags(False, adjoint), _dtype_code(b), nrhs,
+                                    _ptr(b), _ptr(x)))
+        return x
+
+    # -- solves ---------------------------------------------------------------
+    def _solve(self, fn, q, restart, maxit, rtol, out):
+        if q.dtype != torch.complex128:
+            raise TypeError("right-hand sides must be complex128")
+        nrhs = self._vec(q, 0)
+        u = torch.empty_like(q) if out is None else out
+        opts = L.SolveOpts(restart, maxit, rtol)
+        stats = (L.SolveStats * nrhs)()
+        code = L.check(fn(self.handle, nrhs, _ptr(q), _ptr(u), ctypes.byref(opts), stats))
+        info = [dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres) for s in stats]
+        return u, info, code
+
+    def solve(self, q, restart=5, maxit=500, rtol=1e-6, out=None):
+        """u = H^{-1} q by preconditioned FGMRES; returns (u, info, code)."""
+        return self._solve(self.lib.elh_solve, q, restart, maxit, rtol, out)
+
+    def solve_adjoint(self, r, restart=5, maxit=500, rtol=1e-6, out=None):
+        return self._solve(self.lib.elh_solve_adjoint, r, restart, maxit, rtol, out)
+
+    def gradient(self, u, v):
+        nrhs = self._vec(u, 0)
+        g = [torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(3)]
+        L.check(self.lib.elh_gradient(self.handle, nrhs, _ptr(u), _ptr(v), _ptr(g[0]), _ptr(g[1]), _ptr(g[2])))
+        return tuple(g)

@@ -1,0 +1,756 @@
+// Host side of libelh: handle and hierarchy, C-ABI entry points, the
+// multigrid cycle driver and the batched flexible GMRES driver.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <complex>
+#include <vector>
+
+#include "../../include/elh.h"
+#include "elh_internal.h"
+
+using namespace elh;
+typedef std::complex<double> zd;
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(call)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return fail(ELH_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+#define CHK(call)                    \
+  do {                               \
+    int r_ = (call);                 \
+    if (r_ != 0) {                   \
+      if (r_ > 0) r_ = fail(ELH_ERR_HIP, "kernel launch failed: %s (%s)", hipGetErrorString((hipError_t)r_), #call); \
+      return r_;                     \
+    }                                \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+static int ensure(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return 0;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  size_t want = (bytes + 255) & ~(size_t)255;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ELH_ERR_OOM, "device allocation of %zu bytes failed", want);
+  }
+  b.bytes = want;
+  return 0;
+}
+static void release(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+struct LevelData {
+  int n[3];
+  double h;
+  int64_t fs, vs;
+  DevBuf lam, mu, rho, kap, mu32, rho32, kap32;
+  DevBuf b[2], x[2], r[2];  // cycle work per precision (0: f64, 1: f32)
+};
+
+// Krylov workspace for one (level, precision, Z precision) combination.
+struct KrylovWS {
+  DevBuf V, Z, w, t;
+};
+
+struct elh_handle {
+  elh_desc d;
+  hipStream_t st;
+  int nlev;
+  LevelData lv[8];
+  KrylovWS kout[2], kin[2];  // outer (level 0, f64; Z f64/f32), inner (coarsest; f64/f32)
+  DevBuf part, dots, coef, tmpvec;
+  double* hdots = nullptr;  // pinned host mirror
+  double* hcoef = nullptr;
+  int ok = 0;
+};
+
+static size_t csz(int prec) { return prec == 0 ? 16 : 8; }  // bytes per complex entry
+static int prec_of(int dtype) { return dtype == ELH_C64 ? 1 : 0; }
+
+template <typename T>
+static LevelArgs<T> largs(const elh_handle* H, int l, bool shifted) {
+  const LevelData& L = H->lv[l];
+  LevelArgs<T> a;
+  a.n[0] = L.n[0];
+  a.n[1] = L.n[1];
+  a.n[2] = L.n[2];
+  a.fs = L.fs;
+  a.vs = L.vs;
+  a.h = (T)L.h;
+  a.ih = (T)(1.0 / L.h);
+  a.beta = (T)H->d.beta;
+  a.omega2 = (T)(H->d.omega * H->d.omega);
+  a.gam = (T)(H->d.gamma + (shifted ? H->d.alpha : 0.0));
+  a.abl_w = (T)H->d.abl_width;
+  a.abl_amp = (T)H->d.abl_amp;
+  if (sizeof(T) == 8) {
+    a.mu = (const T*)L.mu.p;
+    a.rho = (const T*)L.rho.p;
+    a.kap = (const T*)L.kap.p;
+  } else {
+    a.mu = (const T*)L.mu32.p;
+    a.rho = (const T*)L.rho32.p;
+    a.kap = (const T*)L.kap32.p;
+  }
+  return a;
+}
+
+static int check_desc(const elh_desc* d) {
+  if (!d) return fail(ELH_ERR_ARG, "desc is NULL");
+  if (d->dim != 2 && d->dim != 3) return fail(ELH_ERR_ARG, "dim must be 2 or 3");
+  if (d->levels < 1 || d->levels > 8) return fail(ELH_ERR_ARG, "levels must be in 1..8");
+  for (int a = 0; a < d->dim; ++a) {
+    if (d->n[a] < 2) return fail(ELH_ERR_ARG, "n[%d] must be >= 2", a);
+    int div = 1 << (d->levels - 1);
+    if (d->n[a] % div != 0 || d->n[a] / div < 2)
+      return fail(ELH_ERR_ARG, "n[%d]=%d not divisible by 2^(levels-1) with >= 2 coarse cells", a, d->n[a]);
+  }
+  if (d->dim == 2 && d->n[2] != 1) return fail(ELH_ERR_ARG, "n[2] must be 1 in 2D");
+  if (!(d->h > 0)) return fail(ELH_ERR_ARG, "h must be positive");
+  if (!(d->beta > 0 && d->beta <= 1)) return fail(ELH_ERR_ARG, "beta must be in (0,1]");
+  if (d->nu1 < 0 || d->nu2 < 0) return fail(ELH_ERR_ARG, "nu1/nu2 must be >= 0");
+  if (d->coarse_mode < 0 || d->coarse_mode > 2) return fail(ELH_ERR_ARG, "bad coarse_mode");
+  if (d->coarse_mode == ELH_COARSE_DENSE) return fail(ELH_ERR_ARG, "ELH_COARSE_DENSE is not available in this build");
+  if (d->coarse_mode != ELH_COARSE_DENSE && d->coarse_sweeps < 1) return fail(ELH_ERR_ARG, "coarse_sweeps must be >= 1");
+  if (d->coarse_mode == ELH_COARSE_KRYLOV && (d->coarse_restart < 1 || d->coarse_maxit < 1))
+    return fail(ELH_ERR_ARG, "coarse_restart/coarse_maxit must be >= 1");
+  if (d->coarse_restart + 1 > MAXDOT) return fail(ELH_ERR_ARG, "coarse_restart too large");
+  if (d->precond_dtype != ELH_C64 && d->precond_dtype != ELH_C128) return fail(ELH_ERR_ARG, "bad precond_dtype");
+  if (d->abl_width < 0) return fail(ELH_ERR_ARG, "abl_width must be >= 0");
+  return 0;
+}
+
+static int build_hierarchy(elh_handle* H, const double* lam, const double* mu, const double* rho) {
+  hipStream_t st = H->st;
+  LevelData& L0 = H->lv[0];
+  HIPCHK(hipMemcpyAsync(L0.lam.p, lam, L0.fs * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(L0.mu.p, mu, L0.fs * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(L0.rho.p, rho, L0.fs * 8, hipMemcpyDeviceToDevice, st));
+  for (int l = 1; l < H->nlev; ++l) {
+    LevelData& F = H->lv[l - 1];
+    LevelData& C = H->lv[l];
+    CHK(launch_coarsen_media(H->d.dim, F.n, (const double*)F.lam.p, (double*)C.lam.p, st));
+    CHK(launch_coarsen_media(H->d.dim, F.n, (const double*)F.mu.p, (double*)C.mu.p, st));
+    CHK(launch_coarsen_media(H->d.dim, F.n, (const double*)F.rho.p, (double*)C.rho.p, st));
+  }
+  for (int l = 0; l < H->nlev; ++l) {
+    LevelData& L = H->lv[l];
+    CHK(launch_media_finish(L.fs, (const double*)L.lam.p, (const double*)L.mu.p, (const double*)L.rho.p,
+                            (double*)L.kap.p, (float*)L.mu32.p, (float*)L.rho32.p, (float*)L.kap32.p, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return 0;
+}
+
+extern "C" int elh_create(const elh_desc* desc, const double* lam, const double* mu, const double* rho,
+                          void* stream, elh_handle** out) {
+  if (!out) return fail(ELH_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_desc(desc);
+  if (rc) return rc;
+  if (!lam || !mu || !rho) return fail(ELH_ERR_ARG, "media pointers must be non-NULL device pointers");
+  elh_handle* H = new elh_handle();
+  H->d = *desc;
+  H->st = (hipStream_t)stream;
+  H->nlev = desc->levels;
+  for (int l = 0; l < H->nlev; ++l) {
+    LevelData& L = H->lv[l];
+    for (int a = 0; a < 3; ++a) L.n[a] = (a < desc->dim) ? (desc->n[a] >> l) : 1;
+    L.h = desc->h * (double)(1 << l);
+    L.fs = (int64_t)L.n[0] * L.n[1] * L.n[2];
+    L.vs = (int64_t)(desc->dim + 1) * L.fs;
+    int e = 0;
+    e |= ensure(L.lam, L.fs * 8);
+    e |= ensure(L.mu, L.fs * 8);
+    e |= ensure(L.rho, L.fs * 8);
+    e |= ensure(L.kap, L.fs * 8);
+    e |= ensure(L.mu32, L.fs * 4);
+    e |= ensure(L.rho32, L.fs * 4);
+    e |= ensure(L.kap32, L.fs * 4);
+    if (e) {
+      elh_destroy(H);
+      return ELH_ERR_OOM;
+    }
+  }
+  if (ensure(H->part, (size_t)MAXRHS_KRYLOV * 512 * MAXDOT * 2 * 8) ||
+      ensure(H->dots, MAXRHS_KRYLOV * MAXDOT * 16) || ensure(H->coef, MAXRHS_KRYLOV * MAXDOT * 16)) {
+    elh_destroy(H);
+    return ELH_ERR_OOM;
+  }
+  if (hipHostMalloc((void**)&H->hdots, MAXRHS_KRYLOV * MAXDOT * 16, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&H->hcoef, MAXRHS_KRYLOV * MAXDOT * 16, hipHostMallocDefault) != hipSuccess) {
+    elh_destroy(H);
+    return fail(ELH_ERR_OOM, "pinned host allocation failed");
+  }
+  rc = build_hierarchy(H, lam, mu, rho);
+  if (rc) {
+    elh_destroy(H);
+    return rc;
+  }
+  H->ok = 1;
+  *out = H;
+  return 0;
+}
+
+extern "C" int elh_set_media(elh_handle* H, const double* lam, const double* mu, const double* rho) {
+  if (!H || !H->ok) return fail(ELH_ERR_STATE, "invalid handle");
+  if (!lam || !mu || !rho) return fail(ELH_ERR_ARG, "media pointers must be non-NULL");
+  return build_hierarchy(H, lam, mu, rho);
+}
+
+extern "C" int elh_destroy(elh_handle* H) {
+  if (!H) return 0;
+  if (H->st) (void)hipStreamSynchronize(H->st);
+  else (void)hipDeviceSynchronize();
+  for (int l = 0; l < 8; ++l) {
+    LevelData& L = H->lv[l];
+    release(L.lam); release(L.mu); release(L.rho); release(L.kap);
+    release(L.mu32); release(L.rho32); release(L.kap32);
+    for (int p = 0; p < 2; ++p) { release(L.b[p]); release(L.x[p]); release(L.r[p]); }
+  }
+  for (int p = 0; p < 2; ++p) {
+    KrylovWS* ws[2] = {&H->kout[p], &H->kin[p]};
+    for (auto* w : ws) { release(w->V); release(w->Z); release(w->w); release(w->t); }
+  }
+  release(H->part); release(H->dots); release(H->coef); release(H->tmpvec);
+  if (H->hdots) (void)hipHostFree(H->hdots);
+  if (H->hcoef) (void)hipHostFree(H->hcoef);
+  delete H;
+  return 0;
+}
+
+extern "C" int elh_level_info(elh_handle* H, int level, int* n3, double* hl) {
+  if (!H || !H->ok) return fail(ELH_ERR_STATE, "invalid handle");
+  if (level < 0 || level >= H->nlev) return fail(ELH_ERR_ARG, "level out of range");
+  if (n3) for (int a = 0; a < 3; ++a) n3[a] = H->lv[level].n[a];
+  if (hl) *hl = H->lv[level].h;
+  return H->nlev;
+}
+
+static int check_common(elh_handle* H, int level, int dtype, int nrhs) {
+  if (!H || !H->ok) return fail(ELH_ERR_STATE, "invalid handle");
+  if (level < 0 || level >= H->nlev) return fail(ELH_ERR_ARG, "level %d out of range", level);
+  if (dtype != ELH_C64 && dtype != ELH_C128) return fail(ELH_ERR_ARG, "dtype must be ELH_C64 or ELH_C128");
+  if (nrhs < 1 || nrhs > 65535) return fail(ELH_ERR_ARG, "nrhs must be in 1..65535");
+  return 0;
+}
+
+static int ensure_cycle_bufs(elh_handle* H, int prec, int nrhs) {
+  for (int l = 0; l < H->nlev; ++l) {
+    LevelData& L = H->lv[l];
+    size_t bytes = (size_t)nrhs * L.vs * csz(prec);
+    if (ensure(L.b[prec], bytes) || ensure(L.x[prec], bytes) || ensure(L.r[prec], bytes)) return ELH_ERR_OOM;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// level operations (precision T)
+// ---------------------------------------------------------------------------
+template <typename T>
+static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs) {
+  return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);
+}
+
+static double level_damping(const elh_handle* H, int l) {
+  if (l == H->nlev - 1 && H->d.coarse_damping > 0) return H->d.coarse_damping;
+  return H->d.damping[l < 8 ? l : 7];
+}
+
+// one colour of red-black Vanka; x_is_zero lets the residual be b itself
+template <typename T>
+static int op_relax(elh_handle* H, int l, bool adj, int colour, const void* b, void* x, int nrhs, bool x_is_zero) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  LevelData& L = H->lv[l];
+  const void* r = b;
+  if (!x_is_zero) {
+    CHK(op_apply<T>(H, l, true, adj, x, b, L.r[prec].p, nrhs));
+    r = L.r[prec].p;
+  }
+  return launch_vanka<T>(largs<T>(H, l, true), H->d.dim, adj, r, x, colour, level_damping(H, l), nrhs, H->st);
+}
+
+template <typename T>
+static int op_sweeps_from_zero(elh_handle* H, int l, bool adj, const void* b, void* x, int nrhs, int sweeps) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  CHK(launch_zero(x, (int64_t)nrhs * H->lv[l].vs * csz(prec), H->st));
+  for (int s = 0; s < sweeps; ++s) {
+    CHK(op_relax<T>(H, l, adj, 0, b, x, nrhs, s == 0));
+    CHK(op_relax<T>(H, l, adj, 1, b, x, nrhs, false));
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// batched restarted (flexible) GMRES, right preconditioned
+// ---------------------------------------------------------------------------
+struct GmresStats {
+  std::vector<int> iters, restarts, status;
+  std::vector<double> relres;
+};
+
+// dots[s][i] for i < m, from the device buffer (synchronises)
+static int fetch_dots(elh_handle* H, int nrhs, int m, std::vector<zd>& out) {
+  HIPCHK(hipMemcpyAsync(H->hdots, H->dots.p, (size_t)nrhs * m * 16, hipMemcpyDeviceToHost, H->st));
+  HIPCHK(hipStreamSynchronize(H->st));
+  out.resize((size_t)nrhs * m);
+  for (int i = 0; i < nrhs * m; ++i) out[i] = zd(H->hdots[2 * i], H->hdots[2 * i + 1]);
+  return 0;
+}
+
+static int push_coef(elh_handle* H, const std::vector<zd>& c) {
+  for (size_t i = 0; i < c.size(); ++i) {
+    H->hcoef[2 * i] = c[i].real();
+    H->hcoef[2 * i + 1] = c[i].imag();
+  }
+  HIPCHK(hipMemcpyAsync(H->coef.p, H->hcoef, c.size() * 16, hipMemcpyHostToDevice, H->st));
+  // the pinned staging buffer is reused by the next push: wait for the copy
+  HIPCHK(hipStreamSynchronize(H->st));
+  return 0;
+}
+
+template <typename TX, typename TY>
+static int scale_copy(elh_handle* H, const std::vector<zd>* a, const void* x, int64_t xs, void* y, int64_t ys,
+                      int64_t len, int nrhs) {
+  const double* dev = nullptr;
+  if (a) {
+    CHK(push_coef(H, *a));
+    dev = (const double*)H->coef.p;
+  }
+  return launch_scale_copy<TX, TY>(dev, x, xs, y, ys, len, nrhs, H->st);
+}
+
+
+// AZ: w = A z (z in TZ, w in T); AR: r = b - A x (T vectors);
+// M: z = M v (v in T, z in TZ).  Right-preconditioned flexible GMRES(m),
+// zero initial guess, classical Gram-Schmidt, complex Givens rotations.
+template <typename T, typename TZ, typename OpAZ, typename OpAR, typename OpM>
+static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, OpAR AR, OpM M, const void* b,
+                 void* x, int restart, int maxit, double rtol, GmresStats& st_out) {
+  typedef cx<T> CT;
+  typedef cx<TZ> CZ;
+  const int m = restart;
+  const size_t vbytes = (size_t)nrhs * len * sizeof(CT);
+  const size_t zbytes = (size_t)nrhs * len * sizeof(CZ);
+  if (ensure(ws.V, vbytes * (m + 1)) || ensure(ws.Z, zbytes * m) || ensure(ws.w, vbytes)) return ELH_ERR_OOM;
+  CT* V = (CT*)ws.V.p;
+  CZ* Z = (CZ*)ws.Z.p;
+  CT* w = (CT*)ws.w.p;
+  const int64_t vstr = (int64_t)nrhs * len;  // stride between basis vectors
+  hipStream_t st = H->st;
+  std::vector<zd> dots;
+  // ||b||
+  CHK((launch_multidot<CT, CT>(1, b, 0, len, b, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p, st)));
+  CHK(fetch_dots(H, nrhs, 1, dots));
+  std::vector<double> nb(nrhs), beta(nrhs);
+  for (int s = 0; s < nrhs; ++s) nb[s] = sqrt(dots[s].real());
+  // x = 0, r = b
+  CHK(launch_zero(x, vbytes, st));
+  HIPCHK(hipMemcpyAsync(w, b, vbytes, hipMemcpyDeviceToDevice, st));
+  for (int s = 0; s < nrhs; ++s) beta[s] = nb[s];
+  st_out.iters.assign(nrhs, 0);
+  st_out.restarts.assign(nrhs, 0);
+  st_out.status.assign(nrhs, ELH_NOT_CONVERGED);
+  st_out.relres.assign(nrhs, 1.0);
+  std::vector<char> active(nrhs);
+  int nact = 0;
+  for (int s = 0; s < nrhs; ++s) {
+    if (!(nb[s] > 0)) {
+      active[s] = 0;
+      st_out.status[s] = isfinite(nb[s]) ? ELH_OK : ELH_ERR_NUMERIC;
+      st_out.relres[s] = 0.0;
+    } else {
+      active[s] = rtol < 1.0;
+      if (!active[s]) st_out.status[s] = ELH_OK;
+    }
+    nact += active[s];
+  }
+  int iters = 0;
+  std::vector<zd> Hm((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), sn((size_t)nrhs * m), coef;
+  std::vector<double> cs((size_t)nrhs * m);
+  std::vector<int> jend(nrhs);
+  std::vector<char> live(nrhs);
+  while (nact > 0 && iters < maxit) {
+    // V_0 = r / beta
+    coef.assign(nrhs, zd(0, 0));
+    for (int s = 0; s < nrhs; ++s)
+      if (active[s]) coef[s] = zd(1.0 / beta[s], 0);
+    CHK((scale_copy<CT, CT>(H, &coef, w, len, V, len, len, nrhs)));
+    for (int s = 0; s < nrhs; ++s) {
+      for (int i = 0; i <= m; ++i) g[s * (m + 1) + i] = 0;
+      g[s * (m + 1)] = beta[s];
+      jend[s] = -1;
+      live[s] = active[s];
+    }
+    int j;
+    for (j = 0; j < m; ++j) {
+      CHK(M((const void*)(V + j * vstr), (void*)(Z + j * vstr)));
+      CHK(AZ((const void*)(Z + j * vstr), (void*)w));
+      ++iters;
+      // classical Gram-Schmidt: h = V^H w, w -= V h
+      CHK((launch_multidot<CT, CT>(j + 1, V, vstr, len, w, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p,
+                                   st)));
+      CHK(fetch_dots(H, nrhs, j + 1, dots));
+      coef.assign((size_t)nrhs * (j + 1), zd(0, 0));
+      for (int s = 0; s < nrhs; ++s)
+        for (int i = 0; i <= j; ++i) coef[s * (j + 1) + i] = -dots[s * (j + 1) + i];
+      CHK(push_coef(H, coef));
+      CHK((launch_multiaxpy<CT, CT>(j + 1, (const double*)H->coef.p, V, vstr, len, w, len, len, nrhs, st)));
+      std::vector<zd> hcol = dots;
+      CHK((launch_multidot<CT, CT>(1, w, 0, len, w, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p, st)));
+      CHK(fetch_dots(H, nrhs, 1, dots));
+      coef.assign(nrhs, zd(0, 0));
+      bool any_live = false;
+      for (int s = 0; s < nrhs; ++s) {
+        if (!live[s]) continue;
+        st_out.iters[s]++;
+        double hn = sqrt(dots[s].real());
+        if (!isfinite(hn)) return fail(ELH_ERR_NUMERIC, "non-finite norm in GMRES (rhs %d)", s);
+        zd* hc = &Hm[(size_t)s * (m + 1) * m];
+        for (int i = 0; i <= j; ++i) hc[i * m + j] = hcol[s * (j + 1) + i];
+        hc[(j + 1) * m + j] = hn;
+        coef[s] = hn > 0 ? zd(1.0 / hn, 0) : zd(0, 0);
+        // apply previous rotations
+        for (int i = 0; i < j; ++i) {
+          zd a = hc[i * m + j], bb = hc[(i + 1) * m + j];
+          double c = cs[s * m + i];
+          zd sgn = sn[s * m + i];
+          hc[i * m + j] = c * a + sgn * bb;
+          hc[(i + 1) * m + j] = -std::conj(sgn) * a + c * bb;
+        }
+        zd a = hc[j * m + j], bb = hc[(j + 1) * m + j];
+        double c;
+        zd sgn;
+        if (std::abs(bb) == 0) {
+          c = 1;
+          sgn = 0;
+        } else if (std::abs(a) == 0) {
+          c = 0;
+          sgn = std::conj(bb) / std::abs(bb);
+        } else {
+          double den = hypot(std::abs(a), std::abs(bb));
+          c = std::abs(a) / den;
+          sgn = (a / std::abs(a)) * std::conj(bb) / den;
+        }
+        cs[s * m + j] = c;
+        sn[s * m + j] = sgn;
+        hc[j * m + j] = c * a + sgn * bb;
+        hc[(j + 1) * m + j] = 0;
+        zd* gs = &g[(size_t)s * (m + 1)];
+        gs[j + 1] = -std::conj(sgn) * gs[j];
+        gs[j] = c * gs[j];
+        jend[s] = j;
+        double res = std::abs(gs[j + 1]) / nb[s];
+        if (res <= rtol || hn == 0) live[s] = 0;
+        if (live[s]) any_live = true;
+      }
+      CHK((scale_copy<CT, CT>(H, &coef, w, len, V + (j + 1) * vstr, len, len, nrhs)));
+      if (!any_live || iters >= maxit) {
+        ++j;
+        break;
+      }
+    }
+    // y = H^{-1} g per rhs, then x += Z y
+    int kmax = j;
+    coef.assign((size_t)nrhs * kmax, zd(0, 0));
+    for (int s = 0; s < nrhs; ++s) {
+      if (!active[s]) continue;
+      int k = jend[s] + 1;
+      const zd* hc = &Hm[(size_t)s * (m + 1) * m];
+      const zd* gs = &g[(size_t)s * (m + 1)];
+      std::vector<zd> y(k);
+      for (int i = k - 1; i >= 0; --i) {
+        zd acc = gs[i];
+        for (int q = i + 1; q < k; ++q) acc -= hc[i * m + q] * y[q];
+        y[i] = acc / hc[i * m + i];
+      }
+      for (int i = 0; i < k; ++i) coef[(size_t)s * kmax + i] = y[i];
+    }
+    CHK(push_coef(H, coef));
+    CHK((launch_multiaxpy<CZ, CT>(kmax, (const double*)H->coef.p, Z, vstr, len, x, len, len, nrhs, st)));
+    // true residual r = b - A x
+    CHK(AR((const void*)x, b, (void*)w));
+    CHK((launch_multidot<CT, CT>(1, w, 0, len, w, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p, st)));
+    CHK(fetch_dots(H, nrhs, 1, dots));
+    nact = 0;
+    for (int s = 0; s < nrhs; ++s) {
+      if (!active[s]) continue;
+      st_out.restarts[s]++;
+      beta[s] = sqrt(dots[s].real());
+      if (!isfinite(beta[s])) return fail(ELH_ERR_NUMERIC, "non-finite residual (rhs %d)", s);
+      st_out.relres[s] = beta[s] / nb[s];
+      if (st_out.relres[s] <= rtol) {
+        active[s] = 0;
+        st_out.status[s] = ELH_OK;
+      } else if (beta[s] == 0) {
+        active[s] = 0;
+        st_out.status[s] = ELH_OK;
+      }
+      nact += active[s];
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// coarsest solve and cycle
+// ---------------------------------------------------------------------------
+template <typename T>
+static int coarse_solve(elh_handle* H, bool adj, const void* b, void* x, int nrhs) {
+  const int l = H->nlev - 1;
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const elh_desc& d = H->d;
+  if (d.coarse_mode == ELH_COARSE_RELAX) return op_sweeps_from_zero<T>(H, l, adj, b, x, nrhs, d.coarse_sweeps);
+  if (nrhs > MAXRHS_KRYLOV) return fail(ELH_ERR_ARG, "at most %d right-hand sides with the Krylov coarse solve", MAXRHS_KRYLOV);
+  // ELH_COARSE_KRYLOV: GMRES on H_s preconditioned by Vanka sweeps
+  LevelData& L = H->lv[l];
+  auto AZ = [&](const void* zi, void* wo) { return op_apply<T>(H, l, true, adj, zi, nullptr, wo, nrhs); };
+  auto AR = [&](const void* xi, const void* bi, void* ro) { return op_apply<T>(H, l, true, adj, xi, bi, ro, nrhs); };
+  auto M = [&](const void* v, void* z) { return op_sweeps_from_zero<T>(H, l, adj, v, z, nrhs, d.coarse_sweeps); };
+  GmresStats gs;
+  int rc = gmres<T, T>(H, H->kin[prec], L.vs, nrhs, AZ, AR, M, b, x, d.coarse_restart, d.coarse_maxit,
+                       d.coarse_rtol, gs);
+  return rc < 0 ? rc : 0;
+}
+
+template <typename T>
+static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrhs) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  if (l == H->nlev - 1) return coarse_solve<T>(H, adj, b, x, nrhs);
+  LevelData& L = H->lv[l];
+  LevelData& C = H->lv[l + 1];
+  CHK(launch_zero(x, (int64_t)nrhs * L.vs * csz(prec), H->st));
+  bool zero = true;
+  for (int s = 0; s < H->d.nu1; ++s) {
+    CHK(op_relax<T>(H, l, adj, 0, b, x, nrhs, zero));
+    zero = false;
+    CHK(op_relax<T>(H, l, adj, 1, b, x, nrhs, false));
+  }
+  // coarse right-hand side R (b - H_s x)
+  const void* r = b;
+  if (!zero) {
+    CHK(op_apply<T>(H, l, true, adj, x, b, L.r[prec].p, nrhs));
+    r = L.r[prec].p;
+  }
+  CHK(launch_restrict<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, r, C.b[prec].p, nrhs, H->st));
+  CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
+  CHK(launch_prolong_add<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, C.x[prec].p, x, nrhs, H->st));
+  for (int s = 0; s < H->d.nu2; ++s) {
+    CHK(op_relax<T>(H, l, adj, 0, b, x, nrhs, false));
+    CHK(op_relax<T>(H, l, adj, 1, b, x, nrhs, false));
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: level operations
+// ---------------------------------------------------------------------------
+extern "C" int elh_apply(elh_handle* H, int level, int flags, int dtype, int nrhs, const void* x, void* y) {
+  int rc = check_common(H, level, dtype, nrhs);
+  if (rc) return rc;
+  if (!x || !y || x == y) return fail(ELH_ERR_ARG, "x and y must be distinct non-NULL pointers");
+  bool sh = flags & ELH_SHIFTED, adj = flags & ELH_ADJOINT;
+  if (dtype == ELH_C128) CHK(op_apply<double>(H, level, sh, adj, x, nullptr, y, nrhs));
+  else CHK(op_apply<float>(H, level, sh, adj, x, nullptr, y, nrhs));
+  return 0;
+}
+
+extern "C" int elh_residual(elh_handle* H, int level, int flags, int dtype, int nrhs, const void* b, const void* x,
+                            void* r) {
+  int rc = check_common(H, level, dtype, nrhs);
+  if (rc) return rc;
+  if (!x || !b || !r || x == r) return fail(ELH_ERR_ARG, "b, x, r must be non-NULL and r != x");
+  bool sh = flags & ELH_SHIFTED, adj = flags & ELH_ADJOINT;
+  if (dtype == ELH_C128) CHK(op_apply<double>(H, level, sh, adj, x, b, r, nrhs));
+  else CHK(op_apply<float>(H, level, sh, adj, x, b, r, nrhs));
+  return 0;
+}
+
+extern "C" int elh_restrict_residual(elh_handle* H, int level, int flags, int dtype, int nrhs, const void* b,
+                                     const void* x, void* rc_out) {
+  int rc = check_common(H, level, dtype, nrhs);
+  if (rc) return rc;
+  if (level >= H->nlev - 1) return fail(ELH_ERR_ARG, "no coarser level below %d", level);
+  if (!b || !rc_out) return fail(ELH_ERR_ARG, "b and rc must be non-NULL");
+  const int prec = prec_of(dtype);
+  if (ensure_cycle_bufs(H, prec, nrhs)) return ELH_ERR_OOM;
+  bool adj = flags & ELH_ADJOINT;
+  const void* r = b;
+  if (x) {
+    if (dtype == ELH_C128) CHK(op_apply<double>(H, level, true, adj, x, b, H->lv[level].r[prec].p, nrhs));
+    else CHK(op_apply<float>(H, level, true, adj, x, b, H->lv[level].r[prec].p, nrhs));
+    r = H->lv[level].r[prec].p;
+  }
+  if (dtype == ELH_C128)
+    CHK(launch_restrict<double>(largs<double>(H, level, true), largs<double>(H, level + 1, true), H->d.dim, r, rc_out,
+                                nrhs, H->st));
+  else
+    CHK(launch_restrict<float>(largs<float>(H, level, true), largs<float>(H, level + 1, true), H->d.dim, r, rc_out,
+                               nrhs, H->st));
+  return 0;
+}
+
+extern "C" int elh_prolong_add(elh_handle* H, int level, int dtype, int nrhs, const void* e, void* x) {
+  int rc = check_common(H, level, dtype, nrhs);
+  if (rc) return rc;
+  if (level >= H->nlev - 1) return fail(ELH_ERR_ARG, "no coarser level below %d", level);
+  if (!e || !x) return fail(ELH_ERR_ARG, "e and x must be non-NULL");
+  if (dtype == ELH_C128)
+    CHK(launch_prolong_add<double>(largs<double>(H, level, true), largs<double>(H, level + 1, true), H->d.dim, e, x,
+                                   nrhs, H->st));
+  else
+    CHK(launch_prolong_add<float>(largs<float>(H, level, true), largs<float>(H, level + 1, true), H->d.dim, e, x,
+                                  nrhs, H->st));
+  return 0;
+}
+
+extern "C" int elh_relax(elh_handle* H, int level, int flags, int dtype, int nrhs, int colour, const void* b,
+                         void* x) {
+  int rc = check_common(H, level, dtype, nrhs);
+  if (rc) return rc;
+  if (colour != 0 && colour != 1) return fail(ELH_ERR_ARG, "colour must be 0 or 1");
+  if (!b || !x || b == x) return fail(ELH_ERR_ARG, "b and x must be distinct non-NULL pointers");
+  const int prec = prec_of(dtype);
+  if (ensure_cycle_bufs(H, prec, nrhs)) return ELH_ERR_OOM;
+  bool adj = flags & ELH_ADJOINT;
+  if (dtype == ELH_C128) CHK(op_relax<double>(H, level, adj, colour, b, x, nrhs, false));
+  else CHK(op_relax<float>(H, level, adj, colour, b, x, nrhs, false));
+  return 0;
+}
+
+extern "C" int elh_coarse_solve(elh_handle* H, int flags, int dtype, int nrhs, const void* b, void* x) {
+  int rc = check_common(H, H ? H->nlev - 1 : 0, dtype, nrhs);
+  if (rc) return rc;
+  if (!b || !x || b == x) return fail(ELH_ERR_ARG, "b and x must be distinct non-NULL pointers");
+  const int prec = prec_of(dtype);
+  if (ensure_cycle_bufs(H, prec, nrhs)) return ELH_ERR_OOM;
+  bool adj = flags & ELH_ADJOINT;
+  if (dtype == ELH_C128) CHK(coarse_solve<double>(H, adj, b, x, nrhs));
+  else CHK(coarse_solve<float>(H, adj, b, x, nrhs));
+  return 0;
+}
+
+extern "C" int elh_vcycle(elh_handle* H, int flags, int dtype, int nrhs, const void* b, void* x) {
+  int rc = check_common(H, 0, dtype, nrhs);
+  if (rc) return rc;
+  if (!b || !x || b == x) return fail(ELH_ERR_ARG, "b and x must be distinct non-NULL pointers");
+  const int prec = prec_of(dtype);
+  if (ensure_cycle_bufs(H, prec, nrhs)) return ELH_ERR_OOM;
+  bool adj = flags & ELH_ADJOINT;
+  if (dtype == ELH_C128) CHK(cycle<double>(H, 0, adj, b, x, nrhs));
+  else CHK(cycle<float>(H, 0, adj, b, x, nrhs));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: solves
+// ---------------------------------------------------------------------------
+static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u, const elh_solve_opts* opts,
+                      elh_solve_stats* stats) {
+  int rc = check_common(H, 0, ELH_C128, nrhs);
+  if (rc) return rc;
+  if (!q || !u || q == u) return fail(ELH_ERR_ARG, "q and u must be distinct non-NULL pointers");
+  if (!opts) return fail(ELH_ERR_ARG, "opts is NULL");
+  if (opts->restart < 1 || opts->restart + 1 > MAXDOT) return fail(ELH_ERR_ARG, "restart must be in 1..%d", MAXDOT - 1);
+  if (opts->maxit < 1) return fail(ELH_ERR_ARG, "maxit must be >= 1");
+  if (nrhs > MAXRHS_KRYLOV) return fail(ELH_ERR_ARG, "at most %d right-hand sides per solve", MAXRHS_KRYLOV);
+  const int pprec = prec_of(H->d.precond_dtype);
+  if (ensure_cycle_bufs(H, pprec, nrhs)) return ELH_ERR_OOM;
+  LevelData& L0 = H->lv[0];
+  const int64_t len = L0.vs;
+  GmresStats gs;
+  auto AR = [&](const void* xi, const void* bi, void* ro) {
+    return op_apply<double>(H, 0, false, adj, xi, bi, ro, nrhs);
+  };
+  if (pprec == 0) {
+    auto AZ = [&](const void* zi, void* wo) { return op_apply<double>(H, 0, false, adj, zi, nullptr, wo, nrhs); };
+    auto M = [&](const void* v, void* z) { return cycle<double>(H, 0, adj, v, z, nrhs); };
+    rc = gmres<double, double>(H, H->kout[0], len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol,
+                               gs);
+  } else {
+    // float32 cycle (Section 5.3 mixed precision): v is cast to float32,
+    // the cycle writes z_j in float32, the outer operator and all Krylov
+    // state stay float64.
+    KrylovWS& ws = H->kout[1];
+    if (ensure(ws.t, (size_t)nrhs * len * 16)) return ELH_ERR_OOM;
+    auto M = [&](const void* v, void* z) {
+      CHK((launch_scale_copy<cx<double>, cx<float>>(nullptr, v, len, L0.b[1].p, len, len, nrhs, H->st)));
+      return cycle<float>(H, 0, adj, L0.b[1].p, z, nrhs);
+    };
+    auto AZ = [&](const void* zi, void* wo) {
+      CHK((launch_scale_copy<cx<float>, cx<double>>(nullptr, zi, len, ws.t.p, len, len, nrhs, H->st)));
+      return op_apply<double>(H, 0, false, adj, ws.t.p, nullptr, wo, nrhs);
+    };
+    rc = gmres<double, float>(H, ws, len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol, gs);
+  }
+  if (rc < 0) return rc;
+  int worst = ELH_OK;
+  for (int s = 0; s < nrhs; ++s) {
+    if (stats) {
+      stats[s].iters = gs.iters[s];
+      stats[s].restarts = gs.restarts[s];
+      stats[s].status = gs.status[s];
+      stats[s].relres = gs.relres[s];
+    }
+    if (gs.status[s] != ELH_OK) worst = gs.status[s];
+  }
+  return worst;
+}
+
+extern "C" int elh_solve(elh_handle* H, int nrhs, const void* q, void* u, const elh_solve_opts* opts,
+                         elh_solve_stats* stats) {
+  return solve_impl(H, false, nrhs, q, u, opts, stats);
+}
+
+extern "C" int elh_solve_adjoint(elh_handle* H, int nrhs, const void* r, void* v, const elh_solve_opts* opts,
+                                 elh_solve_stats* stats) {
+  return solve_impl(H, true, nrhs, r, v, opts, stats);
+}
+
+extern "C" int elh_gradient(elh_handle* H, int nrhs, const void* u, const void* v, double* g_lam, double* g_mu,
+                            double* g_rho) {
+  (void)H; (void)nrhs; (void)u; (void)v; (void)g_lam; (void)g_mu; (void)g_rho;
+  return fail(ELH_ERR_STATE, "elh_gradient is not available in this build");
+}
+
+extern "C" const char* elh_status_string(int s) {
+  switch (s) {
+    case ELH_OK: return "ok";
+    case ELH_NOT_CONVERGED: return "not converged";
+    case ELH_ERR_ARG: return "invalid argument";
+    case ELH_ERR_HIP: return "HIP runtime error";
+    case ELH_ERR_NUMERIC: return "numerical breakdown";
+    case ELH_ERR_OOM: return "out of device memory";
+    case ELH_ERR_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* elh_last_error(void) { return g_err; }

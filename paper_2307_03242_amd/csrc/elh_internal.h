@@ -1,0 +1,38 @@
+// Internal declarations shared by the kernel and host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "elh_device.h"
+
+namespace elh {
+
+constexpr int MAXDOT = 16;         // most vectors in one fused multi-dot
+constexpr int MAXRHS_KRYLOV = 64;  // right-hand sides per Krylov solve (reduction buffers)
+
+template <typename T>
+int launch_apply(const LevelArgs<T>& L, int dim, bool adj, const void* x, const void* b, void* y, int nrhs,
+                 hipStream_t st);
+template <typename T>
+int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* x, int colour, double w, int nrhs,
+                 hipStream_t st);
+template <typename T>
+int launch_restrict(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* r, void* rc, int nrhs,
+                    hipStream_t st);
+template <typename T>
+int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* e, void* x, int nrhs,
+                       hipStream_t st);
+int launch_coarsen_media(int dim, const int* nf, const double* a, double* out, hipStream_t st);
+int launch_media_finish(int64_t n, const double* lam, const double* mu, const double* rho, double* kap, float* mu32,
+                        float* rho32, float* kap32, hipStream_t st);
+template <typename TV, typename TW>
+int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_rhs, const void* w,
+                    int64_t wstride_rhs, int64_t len, int nrhs, double* part, double* out, hipStream_t st);
+template <typename TV, typename TW>
+int launch_multiaxpy(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
+                     int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st);
+template <typename TX, typename TY>
+int launch_scale_copy(const double* a, const void* x, int64_t xstride, void* y, int64_t ystride, int64_t len,
+                      int nrhs, hipStream_t st);
+int launch_zero(void* p, int64_t bytes, hipStream_t st);
+
+}  // namespace elh

@@ -1,0 +1,537 @@
+// Reference-structured gfx950 kernels: operator apply / residual (all
+// levels, 2D and 3D, forward and adjoint), red-black full Vanka, MAC
+// restriction and prolongation, media setup and Krylov vector operations.
+// The tuned 3D finest-level stencil kernels live in elh_stencil3d.hip.
+#include "elh_device.h"
+#include "elh_internal.h"
+
+namespace elh {
+
+// ---------------------------------------------------------------------------
+// apply / residual: one thread per cell, the cell's left faces and pressure
+// ---------------------------------------------------------------------------
+template <int DIM, bool ADJ, typename T>
+__global__ void __launch_bounds__(256) k_apply(LevelArgs<T> L, const cx<T>* __restrict__ x,
+                                                const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
+                                                int nrhs) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (cell >= L.fs || s >= nrhs) return;
+  int c[3];
+  c[0] = (int)(cell % L.n[0]);
+  c[1] = (int)((cell / L.n[0]) % L.n[1]);
+  c[2] = (int)(cell / ((int64_t)L.n[0] * L.n[1]));
+  const cx<T>* xs = x + s * L.vs;
+  cx<T>* ys = y + s * L.vs;
+  const cx<T>* bs = b ? b + s * L.vs : nullptr;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    cx<T> v = czero<T>();
+    if (c[k] > 0) {
+      v = eval_u<DIM, ADJ>(xs, L, k, c);
+      if (bs) v = bs[k * L.fs + cell] - v;
+    }
+    ys[k * L.fs + cell] = v;
+  }
+  cx<T> v = eval_p<DIM, ADJ>(xs, L, c);
+  if (bs) v = bs[DIM * L.fs + cell] - v;
+  ys[DIM * L.fs + cell] = v;
+}
+
+template <typename T>
+int launch_apply(const LevelArgs<T>& L, int dim, bool adj, const void* x, const void* b, void* y, int nrhs,
+                 hipStream_t st) {
+  dim3 blk(256), grd((unsigned)((L.fs + 255) / 256), nrhs);
+  const cx<T>* xp = (const cx<T>*)x;
+  const cx<T>* bp = (const cx<T>*)b;
+  cx<T>* yp = (cx<T>*)y;
+  if (dim == 3) {
+    if (adj) hipLaunchKernelGGL((k_apply<3, true, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
+    else hipLaunchKernelGGL((k_apply<3, false, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
+  } else {
+    if (adj) hipLaunchKernelGGL((k_apply<2, true, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
+    else hipLaunchKernelGGL((k_apply<2, false, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
+  }
+  return (int)hipGetLastError();
+}
+template int launch_apply<double>(const LevelArgs<double>&, int, bool, const void*, const void*, void*, int,
+                                  hipStream_t);
+template int launch_apply<float>(const LevelArgs<float>&, int, bool, const void*, const void*, void*, int,
+                                 hipStream_t);
+
+// ---------------------------------------------------------------------------
+// red-black full Vanka: cell block of H_s (Section 2.3, Section 3.2 remark)
+// ---------------------------------------------------------------------------
+// Entries of the forward shifted operator on the DOFs of cell c: for each
+// component k the 2x2 block B_k over its left (face c_k) and right (face
+// c_k+1) faces, the coupling column g_k = (+1/h, -1/h) (u rows, p column),
+// the divergence row d_k = (-s0/h, +s0/h) and kappa.  s0 = beta +
+// (1-beta)/2^(d-1) is the centre weight of the spread difference and
+// s1 = (1-beta)/4 * (1/2)^(d-2) the weight of a neighbouring face of the
+// same component in the spread along x_k of a transverse difference.
+template <int DIM, typename T>
+__device__ void vanka_block(const LevelArgs<T>& L, int k, const int* c, cx<T>* B /*LL,LR,RL,RR*/) {
+  const T s0 = L.beta + (T(1) - L.beta) / T(DIM == 3 ? 4 : 2);
+  const T s1 = (T(1) - L.beta) * T(0.25) * T(DIM == 3 ? 0.5 : 1.0);
+  const T ih2 = L.ih * L.ih;
+  const T cn = (T(1) - L.beta) / T(2 * DIM);
+  int F[2][3];
+#pragma unroll
+  for (int sd = 0; sd < 2; ++sd) {
+    F[sd][0] = c[0]; F[sd][1] = c[1]; F[sd][2] = c[2];
+    F[sd][k] = c[k] + sd;
+  }
+  const bool okL = c[k] >= 1, okR = c[k] + 1 <= L.n[k] - 1;
+  const T muc = L.mu[lin<DIM>(L.n, c)];
+  T sum_e[2] = {T(0), T(0)};
+  T rf[2] = {T(0), T(0)};
+  cx<T> mf[2];
+#pragma unroll
+  for (int sd = 0; sd < 2; ++sd) {
+    const bool ok = sd == 0 ? okL : okR;
+    if (!ok) { mf[sd] = czero<T>(); continue; }
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+      if (l == k) continue;
+      int e[3] = {F[sd][0], F[sd][1], F[sd][2]};
+      e[l] = c[l];
+      sum_e[sd] += mu_edge<DIM>(L, k, l, e);
+      e[l] = c[l] + 1;
+      sum_e[sd] += mu_edge<DIM>(L, k, l, e);
+    }
+    rf[sd] = rho_face<DIM>(L, k, F[sd]);
+    mf[sd] = mass_factor<DIM>(L, k, F[sd]);
+  }
+  // diagonal entries: cells on both sides of the face along k
+  {
+    int cl[3] = {c[0], c[1], c[2]};
+    cl[k] = c[k] - 1;
+    T muL = okL ? L.mu[lin<DIM>(L.n, cl)] : T(0);
+    int cr[3] = {c[0], c[1], c[2]};
+    cr[k] = c[k] + 1;
+    T muR = okR ? L.mu[lin<DIM>(L.n, cr)] : T(0);
+    B[0] = okL ? mk(s0 * ih2 * (muL + muc + sum_e[0]), T(0)) - (L.beta * rf[0]) * mf[0] : mk(T(1), T(0));
+    B[3] = okR ? mk(s0 * ih2 * (muc + muR + sum_e[1]), T(0)) - (L.beta * rf[1]) * mf[1] : mk(T(1), T(0));
+  }
+  if (okL && okR) {
+    B[1] = mk(-muc * s0 * ih2 + s1 * ih2 * sum_e[0], T(0)) - (cn * rf[1]) * mf[0];
+    B[2] = mk(-muc * s0 * ih2 + s1 * ih2 * sum_e[1], T(0)) - (cn * rf[0]) * mf[1];
+  } else {
+    B[1] = czero<T>();
+    B[2] = czero<T>();
+  }
+}
+
+template <int DIM, bool ADJ, typename T>
+__global__ void __launch_bounds__(256) k_vanka(LevelArgs<T> L, const cx<T>* __restrict__ r, cx<T>* __restrict__ x,
+                                                int colour, T w, int nrhs) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (cell >= L.fs || s >= nrhs) return;
+  int c[3];
+  c[0] = (int)(cell % L.n[0]);
+  c[1] = (int)((cell / L.n[0]) % L.n[1]);
+  c[2] = (int)(cell / ((int64_t)L.n[0] * L.n[1]));
+  if (((c[0] + c[1] + c[2]) & 1) != colour) return;
+  const cx<T>* rs = r + s * L.vs;
+  cx<T>* xs = x + s * L.vs;
+  const T s0 = L.beta + (T(1) - L.beta) / T(DIM == 3 ? 4 : 2);
+  // per component: Binv r and Binv g
+  cx<T> yr[DIM][2], yg[DIM][2];
+  cx<T> schur = mk(L.kap[cell], T(0));
+  cx<T> rp = rs[DIM * L.fs + cell];
+  int64_t idx[DIM][2];
+  bool ok[DIM][2];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    cx<T> B[4];
+    vanka_block<DIM, T>(L, k, c, B);
+    ok[k][0] = c[k] >= 1;
+    ok[k][1] = c[k] + 1 <= L.n[k] - 1;
+    int j[3] = {c[0], c[1], c[2]};
+    idx[k][0] = k * L.fs + cell;
+    j[k] = c[k] + 1;
+    idx[k][1] = ok[k][1] ? k * L.fs + lin<DIM>(L.n, j) : 0;
+    cx<T> g[2], d[2];
+    g[0] = mk(ok[k][0] ? L.ih : T(0), T(0));
+    g[1] = mk(ok[k][1] ? -L.ih : T(0), T(0));
+    d[0] = mk(ok[k][0] ? -s0 * L.ih : T(0), T(0));
+    d[1] = mk(ok[k][1] ? s0 * L.ih : T(0), T(0));
+    if (ADJ) {  // block of H^H = conjugate transpose
+      cx<T> t = B[1];
+      B[0] = conj(B[0]); B[3] = conj(B[3]);
+      B[1] = conj(B[2]); B[2] = conj(t);
+      cx<T> g0 = g[0], g1 = g[1];
+      g[0] = conj(d[0]); g[1] = conj(d[1]);
+      d[0] = conj(g0); d[1] = conj(g1);
+    }
+    cx<T> rk[2];
+    rk[0] = ok[k][0] ? rs[idx[k][0]] : czero<T>();
+    rk[1] = ok[k][1] ? rs[idx[k][1]] : czero<T>();
+    cx<T> det = B[0] * B[3] - B[1] * B[2];
+    cx<T> inv00 = cdiv(B[3], det), inv01 = cdiv(-B[1], det), inv10 = cdiv(-B[2], det), inv11 = cdiv(B[0], det);
+    yr[k][0] = inv00 * rk[0] + inv01 * rk[1];
+    yr[k][1] = inv10 * rk[0] + inv11 * rk[1];
+    yg[k][0] = inv00 * g[0] + inv01 * g[1];
+    yg[k][1] = inv10 * g[0] + inv11 * g[1];
+    rp -= d[0] * yr[k][0] + d[1] * yr[k][1];
+    schur -= d[0] * yg[k][0] + d[1] * yg[k][1];
+  }
+  cx<T> dp = cdiv(rp, schur);
+  xs[DIM * L.fs + cell] += w * dp;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+      if (ok[k][sd]) xs[idx[k][sd]] += w * (yr[k][sd] - yg[k][sd] * dp);
+}
+
+template <typename T>
+int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* x, int colour, double w, int nrhs,
+                 hipStream_t st) {
+  dim3 blk(256), grd((unsigned)((L.fs + 255) / 256), nrhs);
+  const cx<T>* rp = (const cx<T>*)r;
+  cx<T>* xp = (cx<T>*)x;
+  if (dim == 3) {
+    if (adj) hipLaunchKernelGGL((k_vanka<3, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else hipLaunchKernelGGL((k_vanka<3, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+  } else {
+    if (adj) hipLaunchKernelGGL((k_vanka<2, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else hipLaunchKernelGGL((k_vanka<2, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+  }
+  return (int)hipGetLastError();
+}
+template int launch_vanka<double>(const LevelArgs<double>&, int, bool, const void*, void*, int, double, int,
+                                  hipStream_t);
+template int launch_vanka<float>(const LevelArgs<float>&, int, bool, const void*, void*, int, double, int,
+                                 hipStream_t);
+
+// ---------------------------------------------------------------------------
+// MAC restriction (one thread per coarse cell) and prolongation (one thread
+// per fine cell), Section 2.3
+// ---------------------------------------------------------------------------
+template <int DIM, typename T>
+__global__ void __launch_bounds__(256) k_restrict(LevelArgs<T> F, LevelArgs<T> C, const cx<T>* __restrict__ r,
+                                                   cx<T>* __restrict__ rc, int nrhs) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (cell >= C.fs || s >= nrhs) return;
+  int c[3];
+  c[0] = (int)(cell % C.n[0]);
+  c[1] = (int)((cell / C.n[0]) % C.n[1]);
+  c[2] = (int)(cell / ((int64_t)C.n[0] * C.n[1]));
+  const cx<T>* rs = r + s * F.vs;
+  cx<T>* os = rc + s * C.vs;
+  const T tw = DIM == 3 ? T(0.25) : T(0.5);  // (1/2)^(d-1) transverse pair means
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    cx<T> acc = czero<T>();
+    if (c[k] >= 1) {
+      for (int o = -1; o <= 1; ++o) {
+        const T wk = o == 0 ? T(0.5) : T(0.25);
+        int nb = DIM == 3 ? 4 : 2;
+        for (int b = 0; b < nb; ++b) {
+          int j[3] = {2 * c[0], 2 * c[1], DIM == 3 ? 2 * c[2] : 0};
+          int bit = 0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            if (a == k) continue;
+            j[a] += (b >> bit) & 1;
+            ++bit;
+          }
+          j[k] = 2 * c[k] + o;
+          acc += (wk * tw) * rs[k * F.fs + lin<DIM>(F.n, j)];
+        }
+      }
+    }
+    os[k * C.fs + cell] = acc;
+  }
+  cx<T> acc = czero<T>();
+  const int nch = DIM == 3 ? 8 : 4;
+  for (int b = 0; b < nch; ++b) {
+    int j[3] = {2 * c[0] + (b & 1), 2 * c[1] + ((b >> 1) & 1), DIM == 3 ? 2 * c[2] + ((b >> 2) & 1) : 0};
+    acc += rs[DIM * F.fs + lin<DIM>(F.n, j)];
+  }
+  os[DIM * C.fs + cell] = (T(1) / T(nch)) * acc;
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(256) k_prolong_add(LevelArgs<T> F, LevelArgs<T> C, const cx<T>* __restrict__ e,
+                                                      cx<T>* __restrict__ x, int nrhs) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (cell >= F.fs || s >= nrhs) return;
+  int i[3];
+  i[0] = (int)(cell % F.n[0]);
+  i[1] = (int)((cell / F.n[0]) % F.n[1]);
+  i[2] = (int)(cell / ((int64_t)F.n[0] * F.n[1]));
+  const cx<T>* es = e + s * C.vs;
+  cx<T>* xs = x + s * F.vs;
+  // 1D interpolation stencils per axis: up to two coarse indices + weights
+  for (int f = 0; f <= DIM; ++f) {
+    if (f < DIM && i[f] == 0) continue;  // boundary face stays zero
+    int J[3][2];
+    T W[3][2];
+    int cnt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cnt[a] = 0;
+      if (a >= DIM) { J[a][0] = 0; W[a][0] = T(1); cnt[a] = 1; continue; }
+      if (a == f) {  // face-normal linear interpolation
+        if ((i[a] & 1) == 0) {
+          int jj = i[a] >> 1;
+          if (jj >= 1 && jj <= C.n[a] - 1) { J[a][cnt[a]] = jj; W[a][cnt[a]] = T(1); ++cnt[a]; }
+        } else {
+          int j0 = (i[a] - 1) >> 1, j1 = (i[a] + 1) >> 1;
+          if (j0 >= 1 && j0 <= C.n[a] - 1) { J[a][cnt[a]] = j0; W[a][cnt[a]] = T(0.5); ++cnt[a]; }
+          if (j1 >= 1 && j1 <= C.n[a] - 1) { J[a][cnt[a]] = j1; W[a][cnt[a]] = T(0.5); ++cnt[a]; }
+        }
+      } else {  // cell linear interpolation, weights 3/4 and 1/4
+        int I = i[a] >> 1;
+        J[a][cnt[a]] = I; W[a][cnt[a]] = T(0.75); ++cnt[a];
+        int I2 = (i[a] & 1) ? I + 1 : I - 1;
+        if (I2 >= 0 && I2 <= C.n[a] - 1) { J[a][cnt[a]] = I2; W[a][cnt[a]] = T(0.25); ++cnt[a]; }
+      }
+    }
+    cx<T> acc = czero<T>();
+    for (int a0 = 0; a0 < cnt[0]; ++a0)
+      for (int a1 = 0; a1 < cnt[1]; ++a1)
+        for (int a2 = 0; a2 < cnt[2]; ++a2) {
+          int j[3] = {J[0][a0], J[1][a1], J[2][a2]};
+          acc += (W[0][a0] * W[1][a1] * W[2][a2]) * es[f * C.fs + lin<DIM>(C.n, j)];
+        }
+    xs[f * F.fs + cell] += acc;
+  }
+}
+
+template <typename T>
+int launch_restrict(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* r, void* rc, int nrhs,
+                    hipStream_t st) {
+  dim3 blk(256), grd((unsigned)((C.fs + 255) / 256), nrhs);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_restrict<3, T>), grd, blk, 0, st, F, C, (const cx<T>*)r, (cx<T>*)rc, nrhs);
+  else
+    hipLaunchKernelGGL((k_restrict<2, T>), grd, blk, 0, st, F, C, (const cx<T>*)r, (cx<T>*)rc, nrhs);
+  return (int)hipGetLastError();
+}
+template <typename T>
+int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* e, void* x, int nrhs,
+                       hipStream_t st) {
+  dim3 blk(256), grd((unsigned)((F.fs + 255) / 256), nrhs);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_prolong_add<3, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
+  else
+    hipLaunchKernelGGL((k_prolong_add<2, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
+  return (int)hipGetLastError();
+}
+template int launch_restrict<double>(const LevelArgs<double>&, const LevelArgs<double>&, int, const void*, void*,
+                                     int, hipStream_t);
+template int launch_restrict<float>(const LevelArgs<float>&, const LevelArgs<float>&, int, const void*, void*, int,
+                                    hipStream_t);
+template int launch_prolong_add<double>(const LevelArgs<double>&, const LevelArgs<double>&, int, const void*,
+                                        void*, int, hipStream_t);
+template int launch_prolong_add<float>(const LevelArgs<float>&, const LevelArgs<float>&, int, const void*, void*,
+                                       int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// media setup: child means, kappa, casts
+// ---------------------------------------------------------------------------
+__global__ void k_coarsen_media(int dim, int f0, int f1, int f2, const double* __restrict__ a, double* __restrict__ out) {
+  const int c0 = f0 / 2, c1 = f1 / 2, c2 = dim == 3 ? f2 / 2 : 1;
+  const int64_t n = (int64_t)c0 * c1 * c2;
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= n) return;
+  int i0 = (int)(cell % c0), i1 = (int)((cell / c0) % c1), i2 = (int)(cell / ((int64_t)c0 * c1));
+  double s = 0.0;
+  const int nz = dim == 3 ? 2 : 1;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < 2; ++y)
+      for (int xx = 0; xx < 2; ++xx) {
+        int64_t j = ((int64_t)(dim == 3 ? 2 * i2 + z : 0) * f1 + (2 * i1 + y)) * f0 + (2 * i0 + xx);
+        s += a[j];
+      }
+  // mean of the 2^d children, summed in the order x1 pairs, then x2, x3
+  out[cell] = s / (double)(dim == 3 ? 8 : 4);
+}
+
+__global__ void k_media_finish(int64_t n, const double* __restrict__ lam, const double* __restrict__ mu,
+                               const double* __restrict__ rho, double* __restrict__ kap, float* __restrict__ mu32,
+                               float* __restrict__ rho32, float* __restrict__ kap32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double k = 1.0 / (lam[i] + mu[i]);
+  kap[i] = k;
+  mu32[i] = (float)mu[i];
+  rho32[i] = (float)rho[i];
+  kap32[i] = (float)k;
+}
+
+int launch_coarsen_media(int dim, const int* nf, const double* a, double* out, hipStream_t st) {
+  int64_t n = (int64_t)(nf[0] / 2) * (nf[1] / 2) * (dim == 3 ? nf[2] / 2 : 1);
+  hipLaunchKernelGGL(k_coarsen_media, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dim, nf[0], nf[1],
+                     nf[2], a, out);
+  return (int)hipGetLastError();
+}
+int launch_media_finish(int64_t n, const double* lam, const double* mu, const double* rho, double* kap, float* mu32,
+                        float* rho32, float* kap32, hipStream_t st) {
+  hipLaunchKernelGGL(k_media_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lam, mu, rho, kap,
+                     mu32, rho32, kap32);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vector operations on batches of complex vectors (nrhs x len).
+// Reductions accumulate in float64, two stages, fixed order.
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_THREADS = 256;
+
+template <typename TV, typename TW>
+__global__ void __launch_bounds__(RED_THREADS) k_multidot(int m, const TV* __restrict__ V, int64_t vstride_vec,
+                                                           int64_t vstride_rhs, const TW* __restrict__ w,
+                                                           int64_t wstride_rhs, int64_t len,
+                                                           double* __restrict__ part) {
+  // part[(s*RED_BLOCKS + block)*m*2 + 2i (+1)] = partial of <V_i, w>
+  const int s = blockIdx.y;
+  double acc_re[MAXDOT], acc_im[MAXDOT];
+#pragma unroll
+  for (int i = 0; i < MAXDOT; ++i) { acc_re[i] = 0; acc_im[i] = 0; }
+  const TW* ws = w + s * wstride_rhs;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
+    auto wv = ws[t];
+    double wr = (double)wv.re, wi = (double)wv.im;
+#pragma unroll
+    for (int i = 0; i < MAXDOT; ++i) {
+      if (i < m) {
+        auto vv = V[i * vstride_vec + s * vstride_rhs + t];
+        double vr = (double)vv.re, vi = (double)vv.im;
+        acc_re[i] += vr * wr + vi * wi;  // conj(v) * w
+        acc_im[i] += vr * wi - vi * wr;
+      }
+    }
+  }
+  __shared__ double red[RED_THREADS];
+  for (int i = 0; i < m; ++i) {
+    for (int part_ri = 0; part_ri < 2; ++part_ri) {
+      red[threadIdx.x] = part_ri == 0 ? acc_re[i] : acc_im[i];
+      __syncthreads();
+      for (int o = RED_THREADS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) part[((int64_t)s * gridDim.x + blockIdx.x) * m * 2 + 2 * i + part_ri] = red[0];
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_reduce_parts(int m2, int nblocks, const double* __restrict__ part, double* __restrict__ out) {
+  // one thread per (rhs, entry); fixed summation order over blocks
+  const int s = blockIdx.x;
+  const int e = threadIdx.x;
+  if (e >= m2) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblocks; ++b) acc += part[((int64_t)s * nblocks + b) * m2 + e];
+  out[(int64_t)s * m2 + e] = acc;
+}
+
+template <typename TV, typename TW>
+int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_rhs, const void* w,
+                    int64_t wstride_rhs, int64_t len, int nrhs, double* part, double* out, hipStream_t st) {
+  int nb = (int)((len + RED_THREADS - 1) / RED_THREADS);
+  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL((k_multidot<TV, TW>), dim3(nb, nrhs), dim3(RED_THREADS), 0, st, m, (const TV*)V, vstride_vec,
+                     vstride_rhs, (const TW*)w, wstride_rhs, len, part);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(64), 0, st, 2 * m, nb, part, out);
+  return (int)hipGetLastError();
+}
+template int launch_multidot<cx<double>, cx<double>>(int, const void*, int64_t, int64_t, const void*, int64_t,
+                                                     int64_t, int, double*, double*, hipStream_t);
+template int launch_multidot<cx<float>, cx<float>>(int, const void*, int64_t, int64_t, const void*, int64_t,
+                                                   int64_t, int, double*, double*, hipStream_t);
+
+// w[s] += sum_i coef[s*m+i] * V_i[s]   (coef complex double, on device)
+template <typename TV, typename TW>
+__global__ void __launch_bounds__(256) k_multiaxpy(int m, const double* __restrict__ coef, const TV* __restrict__ V,
+                                                    int64_t vstride_vec, int64_t vstride_rhs, TW* __restrict__ w,
+                                                    int64_t wstride_rhs, int64_t len) {
+  const int s = blockIdx.y;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  auto wv = w[s * wstride_rhs + t];
+  double re = (double)wv.re, im = (double)wv.im;
+  for (int i = 0; i < m; ++i) {
+    double cr = coef[(s * m + i) * 2], ci = coef[(s * m + i) * 2 + 1];
+    auto vv = V[i * vstride_vec + s * vstride_rhs + t];
+    double vr = (double)vv.re, vi = (double)vv.im;
+    re += cr * vr - ci * vi;
+    im += cr * vi + ci * vr;
+  }
+  wv.re = re;
+  wv.im = im;
+  w[s * wstride_rhs + t] = wv;
+}
+
+template <typename TV, typename TW>
+int launch_multiaxpy(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
+                     int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_multiaxpy<TV, TW>), dim3((unsigned)((len + 255) / 256), nrhs), dim3(256), 0, st, m, coef,
+                     (const TV*)V, vstride_vec, vstride_rhs, (TW*)w, wstride_rhs, len);
+  return (int)hipGetLastError();
+}
+template int launch_multiaxpy<cx<double>, cx<double>>(int, const double*, const void*, int64_t, int64_t, void*,
+                                                      int64_t, int64_t, int, hipStream_t);
+template int launch_multiaxpy<cx<float>, cx<double>>(int, const double*, const void*, int64_t, int64_t, void*,
+                                                     int64_t, int64_t, int, hipStream_t);
+template int launch_multiaxpy<cx<float>, cx<float>>(int, const double*, const void*, int64_t, int64_t, void*,
+                                                    int64_t, int64_t, int, hipStream_t);
+
+// y[s] = a[s] * x[s]   (a complex double per rhs), with type conversion
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) k_scale_copy(const double* __restrict__ a, const TX* __restrict__ x,
+                                                     int64_t xstride, TY* __restrict__ y, int64_t ystride,
+                                                     int64_t len) {
+  const int s = blockIdx.y;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  double ar = a ? a[2 * s] : 1.0, ai = a ? a[2 * s + 1] : 0.0;
+  auto xv = x[s * xstride + t];
+  double xr = (double)xv.re, xi = (double)xv.im;
+  TY out;
+  out.re = ar * xr - ai * xi;
+  out.im = ar * xi + ai * xr;
+  y[s * ystride + t] = out;
+}
+
+template <typename TX, typename TY>
+int launch_scale_copy(const double* a, const void* x, int64_t xstride, void* y, int64_t ystride, int64_t len,
+                      int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_copy<TX, TY>), dim3((unsigned)((len + 255) / 256), nrhs), dim3(256), 0, st, a,
+                     (const TX*)x, xstride, (TY*)y, ystride, len);
+  return (int)hipGetLastError();
+}
+template int launch_scale_copy<cx<double>, cx<double>>(const double*, const void*, int64_t, void*, int64_t, int64_t,
+                                                       int, hipStream_t);
+template int launch_scale_copy<cx<double>, cx<float>>(const double*, const void*, int64_t, void*, int64_t, int64_t,
+                                                      int, hipStream_t);
+template int launch_scale_copy<cx<float>, cx<double>>(const double*, const void*, int64_t, void*, int64_t, int64_t,
+                                                      int, hipStream_t);
+template int launch_scale_copy<cx<float>, cx<float>>(const double*, const void*, int64_t, void*, int64_t, int64_t,
+                                                     int, hipStream_t);
+
+__global__ void k_fill_zero(uint2* p, int64_t n8) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n8; i += (int64_t)gridDim.x * blockDim.x) p[i] = make_uint2(0, 0);
+}
+int launch_zero(void* p, int64_t bytes, hipStream_t st) {
+  // every vector here is a whole number of 8-byte complex64 entries or wider
+  int64_t n8 = bytes / 8;
+  if (n8 == 0) return 0;
+  int64_t nb = (n8 + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, st, (uint2*)p, n8);
+  return (int)hipGetLastError();
+}
+
+}  // namespace elh

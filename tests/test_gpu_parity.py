@@ -1,0 +1,258 @@
+"""GPU parity: every C-ABI level operation against the CPU oracle.
+
+Inputs come from the seeded generators in `synthetic`; expected values from
+`oracle` only.  Float64 tolerances follow the operator's arithmetic
+(a few hundred terms of size ~max|y| per output: 1e-12 relative), float32
+ones the single-precision unit roundoff times the same term count.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import grid as G
+from oracle import operator as O
+from oracle import transfer as T
+from oracle import cycle as C
+from oracle.smoother import Vanka
+from synthetic import make_media, random_field, point_source, omega_for_ppw
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 3e-5
+
+
+def _params(shape, levels=3, alpha=0.3, seed=3, abl=None, coarse="relax", beta=2 / 3):
+    m = make_media(shape, seed)
+    h = 1.0
+    om = omega_for_ppw(m["vs"].min(), h, 10)
+    abl_w = abl if abl is not None else 0.25 * min(shape) * h
+    return dict(media=m, h=h, omega=om, gamma=0.01, alpha=alpha, beta=beta, abl_width=abl_w,
+                abl_amp=2.0, levels=levels, damping=(0.55, 0.35, 0.25), coarse=coarse)
+
+
+def _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6, precond=torch.complex128):
+    from paper_2307_03242_amd import Problem
+    m = P["media"]
+    return Problem(torch.from_numpy(m["lam"]), torch.from_numpy(m["mu"]), torch.from_numpy(m["rho"]),
+                   h=P["h"], omega=P["omega"], gamma=P["gamma"], alpha=P["alpha"], beta=P["beta"],
+                   abl_width=P["abl_width"], abl_amp=P["abl_amp"], levels=P["levels"],
+                   damping=P["damping"], coarse_mode=P["coarse"], coarse_sweeps=coarse_sweeps,
+                   coarse_restart=5, coarse_maxit=coarse_maxit, coarse_rtol=0.0,
+                   precond_dtype=precond)
+
+
+def _oracle_levels(P, shape):
+    m = P["media"]
+    lv = G.Level(tuple(reversed(shape)), P["h"], P["omega"], P["gamma"], P["beta"], m["lam"], m["mu"],
+                 m["rho"], abl_width=P["abl_width"], abl_amp=P["abl_amp"])
+    lvs = [lv]
+    for _ in range(P["levels"] - 1):
+        lvs.append(C.coarsen_level(lvs[-1]))
+    return lvs
+
+
+def _dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().to(torch.complex128).numpy()
+
+
+def _relerr(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def _maxrel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+SHAPES = [(8, 12, 16), (6, 10, 14), (12, 20), (18, 26)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shifted", [False, True])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_apply_f64(shape, shifted, adjoint):
+    lvls = 2 if min(shape) % 4 else 3
+    P = _params(shape, levels=lvls)
+    prob = _gpu_problem(P, shape)
+    lvs = _oracle_levels(P, shape)
+    for level, lv in enumerate(lvs):
+        lshape = lv.np_shape
+        x = random_field(lshape, 11 + level, nrhs=2)
+        y = _host(prob.apply(_dev(x), level=level, shifted=shifted, adjoint=adjoint))
+        ref = O.apply(lv, x, shift=P["alpha"] if shifted else 0.0, adjoint=adjoint)
+        assert _maxrel(y, ref) <= TOL64, (level, _maxrel(y, ref))
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16), (12, 20)])
+def test_apply_f32(shape):
+    P = _params(shape, levels=2)
+    prob = _gpu_problem(P, shape)
+    lv = _oracle_levels(P, shape)[0]
+    x = random_field(shape, 5, nrhs=3)
+    for shifted in (False, True):
+        for adj in (False, True):
+            y = _host(prob.apply(_dev(x, torch.complex64), shifted=shifted, adjoint=adj))
+            ref = O.apply(lv, x.astype(np.complex64).astype(np.complex128),
+                          shift=P["alpha"] if shifted else 0.0, adjoint=adj)
+            assert _relerr(y, ref) <= TOL32
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16), (12, 20)])
+def test_residual(shape):
+    P = _params(shape, levels=2)
+    prob = _gpu_problem(P, shape)
+    lv = _oracle_levels(P, shape)[0]
+    x = random_field(shape, 6, nrhs=2)
+    b = random_field(shape, 7, nrhs=2)
+    r = _host(prob.residual(_dev(b), _dev(x), shifted=True))
+    ref = b - O.apply(lv, x, shift=P["alpha"])
+    assert _maxrel(r, ref) <= TOL64
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16), (12, 20)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_restrict_residual(shape, adjoint):
+    P = _params(shape, levels=2)
+    prob = _gpu_problem(P, shape)
+    lv, lvc = _oracle_levels(P, shape)
+    x = random_field(shape, 8, nrhs=2)
+    b = random_field(shape, 9, nrhs=2)
+    rc = _host(prob.restrict_residual(_dev(b), _dev(x), adjoint=adjoint))
+    ref = np.stack([T.restrict(lv, b[s] - O.apply(lv, x[s], shift=P["alpha"], adjoint=adjoint), lvc)
+                    for s in range(2)])
+    assert _maxrel(rc, ref) <= TOL64
+    rc0 = _host(prob.restrict_residual(_dev(b)))
+    ref0 = np.stack([T.restrict(lv, b[s], lvc) for s in range(2)])
+    assert _maxrel(rc0, ref0) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16), (12, 20)])
+def test_prolong_add(shape):
+    P = _params(shape, levels=2)
+    prob = _gpu_problem(P, shape)
+    lv, lvc = _oracle_levels(P, shape)
+    x = random_field(shape, 10, nrhs=2)
+    e = random_field(lvc.np_shape, 11, nrhs=2)
+    out = _host(prob.prolong_add(_dev(e), _dev(x)))
+    ref = np.stack([x[s] + T.prolong(lv, e[s], lvc) for s in range(2)])
+    assert _maxrel(out, ref) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16), (6, 10, 14), (12, 20)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_relax_half_sweep(shape, adjoint):
+    P = _params(shape, levels=2)
+    prob = _gpu_problem(P, shape)
+    lv = _oracle_levels(P, shape)[0]
+    A = O.assemble(lv, shift=P["alpha"])
+    if adjoint:
+        A = A.conj().T.tocsr()
+    vk = Vanka(lv, A)
+    x = random_field(shape, 12, nrhs=1)[0]
+    b = random_field(shape, 13, nrhs=1)[0]
+    xg = _dev(x)
+    for colour in (0, 1):
+        prob.relax(_dev(b), xg, colour, adjoint=adjoint)
+        xr = vk.half_sweep(G.pack(lv, x), G.pack(lv, b), P["damping"][0], colour)
+        x = G.unpack(lv, xr)
+        assert _maxrel(_host(xg), x) <= 1e-12
+
+
+@pytest.mark.parametrize("coarse", ["relax", "krylov"])
+@pytest.mark.parametrize("shape,levels", [((8, 12, 16), 3), ((16, 16, 16), 2), ((24, 32), 3)])
+def test_vcycle_f64(shape, levels, coarse):
+    P = _params(shape, levels=levels, coarse=coarse)
+    prob = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6)
+    lv = _oracle_levels(P, shape)[0]
+    cp = C.CycleParams(levels=levels, alpha=P["alpha"], damping=P["damping"], coarse=coarse,
+                       coarse_sweeps=2, coarse_restart=5, coarse_maxit=6, coarse_rtol=0.0)
+    hier = C.Hierarchy(lv, cp)
+    b = random_field(shape, 14, nrhs=2)
+    x = _host(prob.vcycle(_dev(b)))
+    ref = np.stack([hier.vcycle_storage(b[s]) for s in range(2)])
+    assert _relerr(x, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16)])
+def test_vcycle_adjoint_f64(shape):
+    P = _params(shape, levels=3, coarse="relax")
+    prob = _gpu_problem(P, shape)
+    lv = _oracle_levels(P, shape)[0]
+    cp = C.CycleParams(levels=3, alpha=P["alpha"], damping=P["damping"], coarse="relax", coarse_sweeps=2)
+    hier = C.Hierarchy(lv, cp, adjoint=True)
+    b = random_field(shape, 15, nrhs=1)
+    x = _host(prob.vcycle(_dev(b), adjoint=True))
+    assert _relerr(x[0], hier.vcycle_storage(b[0])) <= 1e-11
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16)])
+def test_vcycle_f32_close_to_f64(shape):
+    P = _params(shape, levels=3, coarse="relax")
+    prob = _gpu_problem(P, shape)
+    lv = _oracle_levels(P, shape)[0]
+    hier = C.Hierarchy(lv, C.CycleParams(levels=3, alpha=P["alpha"], damping=P["damping"],
+                                         coarse="relax", coarse_sweeps=2))
+    b = random_field(shape, 16, nrhs=1)
+    x = _host(prob.vcycle(_dev(b, torch.complex64)))
+    assert _relerr(x[0], hier.vcycle_storage(b[0])) <= 1e-4
+
+
+@pytest.mark.parametrize("shape,levels", [((16, 16, 16), 3), ((32, 48), 3)])
+def test_solve_f64_matches_direct(shape, levels):
+    import scipy.sparse.linalg as spla
+    P = _params(shape, levels=levels, coarse="krylov")
+    prob = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=10)
+    lv = _oracle_levels(P, shape)[0]
+    q = point_source(shape)[None]
+    u, info, code = prob.solve(_dev(q), restart=5, maxit=300, rtol=1e-10)
+    assert code == 0 and info[0]["relres"] <= 1e-10
+    ref = spla.spsolve(O.assemble(lv).tocsc(), G.pack(lv, q[0]))
+    err = np.linalg.norm(G.pack(lv, _host(u)[0]) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-7
+    # true residual in float64 through the oracle operator
+    res = np.linalg.norm(G.pack(lv, q[0] - O.apply(lv, _host(u)[0]))) / np.linalg.norm(G.pack(lv, q[0]))
+    assert res <= 1.5e-10
+
+
+def test_solve_mixed_precision_matches_f64():
+    """float32 cycle inside float64 FGMRES to 1e-6: forward error against
+    the float64 direct solution within 1e-5."""
+    import scipy.sparse.linalg as spla
+    shape = (16, 16, 16)
+    P = _params(shape, levels=3, coarse="krylov")
+    prob = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=10, precond=torch.complex64)
+    lv = _oracle_levels(P, shape)[0]
+    q = point_source(shape)[None]
+    u, info, code = prob.solve(_dev(q), restart=5, maxit=300, rtol=1e-6)
+    assert code == 0 and info[0]["relres"] <= 1e-6
+    ref = spla.spsolve(O.assemble(lv).tocsc(), G.pack(lv, q[0]))
+    err = np.linalg.norm(G.pack(lv, _host(u)[0]) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-5
+
+
+def test_solve_batched_rhs_independent():
+    shape = (16, 16, 16)
+    P = _params(shape, levels=3, coarse="relax")
+    prob = _gpu_problem(P, shape, coarse_sweeps=4)
+    q = np.stack([point_source(shape), random_field(shape, 40)])
+    ub, infob, _ = prob.solve(_dev(q), rtol=1e-8, maxit=300)
+    for s in range(2):
+        u1, info1, _ = prob.solve(_dev(q[s:s + 1]), rtol=1e-8, maxit=300)
+        assert _relerr(_host(ub)[s], _host(u1)[0]) <= 1e-6
+        assert infob[s]["relres"] <= 1e-8
+
+
+def test_argument_errors_on_gpu():
+    shape = (8, 8, 8)
+    P = _params(shape, levels=2)
+    prob = _gpu_problem(P, shape)
+    x = _dev(random_field(shape, 1))
+    y = torch.empty_like(x)
+    assert prob.lib.elh_apply(prob.handle, 5, 0, 2, 1, x.data_ptr(), y.data_ptr()) == -1
+    assert prob.lib.elh_apply(prob.handle, 0, 0, 2, 1, x.data_ptr(), x.data_ptr()) == -1
+    with pytest.raises(ValueError):
+        prob.apply(_dev(random_field((8, 8, 6), 1)))
