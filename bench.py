@@ -1,0 +1,209 @@
+"""Benchmark: 256^3 elastic Helmholtz solves per second, float32-preconditioned
+vs float64, and the stencil apply's HBM bandwidth.
+
+Workload (default): 3D 256^3 grid, layered synthetic medium from seed 3
+(Vp in [1.5, 4.5] with Gaussian perturbations, Vs = Vp/1.73,
+rho = 0.25 + 0.5 Vp), h = 1, 10 points per minimal shear wavelength,
+gamma = 0.01, absorbing layer of 16 cells, one point source (u_3 at the
+centre face); beta = 2/3; flexible GMRES(5) in float64 to a 1e-6 relative
+residual, right-preconditioned by 4-level W(1,1)-cycles on the shifted operator (alpha = 0.5; the V-cycle
+is available with --cycle V).
+One step = one complete solve from a zero initial guess.  The headline
+value is the solve rate with the float32 cycle; the same solve with the
+float64 cycle is timed beside it.
+
+Prints ONE JSON line (rank 0).  `python bench.py --gpus N` with N > 1 exits:
+this build runs on one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak, GB/s
+APPLY_BYTES_F64 = 152      # algorithmic bytes per cell of one operator apply (x, y, mu, rho, kappa)
+APPLY_BYTES_F32 = 76
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="cells per axis")
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--alpha", type=float, default=0.5)
+    ap.add_argument("--damping", type=str, default="0.55,0.35,0.25,0.25")
+    ap.add_argument("--abl", type=int, default=16, help="absorbing layer width in cells")
+    ap.add_argument("--coarse", type=str, default="krylov")
+    ap.add_argument("--cycle", type=str, default="W", choices=["V", "W"])
+    ap.add_argument("--coarse-sweeps", type=int, default=2)
+    ap.add_argument("--coarse-maxit", type=int, default=10)
+    ap.add_argument("--coarse-rtol", type=float, default=0.0)
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--maxit", type=int, default=400)
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=64, help="oracle sample grid (cells per axis)")
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    return ap.parse_args()
+
+
+def cpu_baseline(args, gpu_iters, cfg):
+    """Oracle (plain NumPy/SciPy float64) on the host: the same solver on a
+    --cpu-n^3 grid of the same media recipe, timed over --cpu-iters outer
+    FGMRES iterations (hierarchy setup excluded), scaled per cell to the
+    benchmark grid and multiplied by the GPU's iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import grid as G, operator as O, cycle as C
+    from oracle.krylov import fgmres
+    from synthetic import make_media, point_source, omega_for_ppw
+    n = args.cpu_n
+    shape = (n, n, n)
+    m = make_media(shape, args.seed)
+    om = omega_for_ppw(m["vs"].min(), 1.0, 10)
+    lv = G.Level(shape, 1.0, om, 0.01, 2 / 3, m["lam"], m["mu"], m["rho"],
+                 abl_width=args.abl * n / args.n, abl_amp=2.0)
+    with threadpool_limits(limits=1):
+        hier = C.Hierarchy(lv, C.CycleParams(levels=args.levels, alpha=args.alpha,
+                                             damping=cfg["damping"], coarse=args.coarse,
+                                             coarse_sweeps=args.coarse_sweeps,
+                                             coarse_maxit=args.coarse_maxit, coarse_rtol=args.coarse_rtol,
+                                             calls=2 if args.cycle == "W" else 1))
+        A = O.assemble(lv)
+        b = G.pack(lv, point_source(shape))
+        t0 = time.perf_counter()
+        _, info = fgmres(lambda v: A @ v, b, precond=hier.vcycle, restart=5, tol=0.0,
+                         maxit=args.cpu_iters)
+        dt = time.perf_counter() - t0
+    per_iter_cell = dt / info["iters"] / (n ** 3)
+    t_solve = per_iter_cell * (args.n ** 3) * gpu_iters
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "%d outer FGMRES(5)+V-cycle iterations of the float64 oracle on a %d^3 grid "
+                      "(same media recipe, %.1f s), scaled per cell to %d^3 and to the GPU's %d iterations"
+                      % (info["iters"], n, dt, args.n, gpu_iters)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each source/problem would shard independently across GPUs).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2307_03242_amd import Problem
+    from synthetic import make_media, point_source, omega_for_ppw
+
+    torch.cuda.set_device(0)
+    n = args.n
+    shape = (n, n, n)
+    m = make_media(shape, args.seed)
+    h = 1.0
+    omega = omega_for_ppw(m["vs"].min(), h, 10)
+    damping = [float(v) for v in args.damping.split(",")]
+    cfg = dict(h=h, omega=omega, gamma=0.01, alpha=args.alpha, beta=2 / 3, abl_width=args.abl * h,
+               abl_amp=2.0, levels=args.levels, nu1=1, nu2=1, cycle=args.cycle, damping=damping, coarse_mode=args.coarse,
+               coarse_sweeps=args.coarse_sweeps, coarse_restart=5, coarse_maxit=args.coarse_maxit,
+               coarse_rtol=args.coarse_rtol)
+    lam = torch.from_numpy(m["lam"]).cuda()
+    mu = torch.from_numpy(m["mu"]).cuda()
+    rho = torch.from_numpy(m["rho"]).cuda()
+    q = torch.from_numpy(point_source(shape)[None]).cuda()
+    stream = torch.cuda.current_stream()
+
+    def timed_solves(prob):
+        u = torch.empty_like(q)
+        infos = []
+        for _ in range(args.warmup):
+            prob.solve(q, rtol=args.rtol, maxit=args.maxit, out=u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, info, code = prob.solve(q, rtol=args.rtol, maxit=args.maxit, out=u)
+            infos.append(info[0])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, infos, u
+
+    p64 = Problem(lam, mu, rho, precond_dtype=torch.complex128, **cfg)
+    t64, info64, u64 = timed_solves(p64)
+    u64 = u64.clone()
+    del p64
+    torch.cuda.empty_cache()
+    p32 = Problem(lam, mu, rho, precond_dtype=torch.complex64, **cfg)
+    t32, info32, u32 = timed_solves(p32)
+    rel_diff = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
+
+    # stencil apply bandwidth, HIP events on the stream the library uses
+    from synthetic import random_field
+    x = torch.from_numpy(random_field(shape, 1)).cuda()
+    apply = {}
+    for name, dt, nbytes in (("f64", torch.complex128, APPLY_BYTES_F64), ("f32", torch.complex64, APPLY_BYTES_F32)):
+        xx = x.to(dt)
+        yy = torch.empty_like(xx)
+        p32.apply(xx, out=yy)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.apply_reps):
+            p32.apply(xx, out=yy)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.apply_reps
+        apply[name] = dict(ms=ms, gbs=nbytes * n ** 3 / (ms * 1e-3) / 1e9)
+    del x
+
+    value = 1.0 / t32
+    it32 = int(np.median([i["iters"] for i in info32]))
+    it64 = int(np.median([i["iters"] for i in info64]))
+    out = {
+        "metric": "256^3 solves/s to 1e-6 residual, FP32-precond vs FP64; stencil HBM GB/s",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 cycle / c128 Krylov",
+        "data": "synthetic",
+        "config": {
+            "workload": "3D %d^3 elastic Helmholtz, layered+Gaussian media seed %d, 10 ppw, gamma 0.01, "
+                        "ABL %d, 1 point source; FGMRES(5) to %.0e with %d-level %s(1,1) on the shifted "
+                        "operator (alpha %.2f), float32 cycle" % (n, args.seed, args.abl, args.rtol,
+                                                                  args.levels, args.cycle, args.alpha),
+            "grid": [n, n, n], "levels": args.levels, "cycle": args.cycle, "alpha": args.alpha, "beta": 2 / 3,
+            "coarse": "%s(sweeps=%d, maxit=%d)" % (args.coarse, args.coarse_sweeps, args.coarse_maxit),
+            "parallelism": "single GPU",
+        },
+        "fp64": {"solves_per_s": 1.0 / t64, "ms_per_solve": t64 * 1e3, "iters": it64,
+                 "relres": info64[-1]["relres"]},
+        "fp32_precond": {"solves_per_s": value, "iters": it32, "relres": info32[-1]["relres"],
+                         "rel_diff_vs_fp64_solution": rel_diff},
+        "speedup_fp32_vs_fp64": t64 / t32,
+        "apply": {"f64_ms": apply["f64"]["ms"], "f64_GBps": apply["f64"]["gbs"],
+                  "f32_ms": apply["f32"]["ms"], "f32_GBps": apply["f32"]["gbs"]},
+        "roofline": {"bound": "hbm", "achieved": apply["f64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": apply["f64"]["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "operator apply, complex128, %d^3 (152 B/cell)" % n},
+    }
+    del p32
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(args, it32, cfg)
+        except Exception as e:  # report, never hide
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -8,7 +8,9 @@ Test infrastructure (see the package header).
   specified by the paper; reading: arithmetic mean of the 2^d child cells
   of lam, mu, rho; the absorbing layer keeps its physical width.
 * Cycle: Algorithm 1 (two-grid cycle) applied recursively with one
-  recursive call (V-cycle), nu1 pre- and nu2 post-relaxations with
+  recursive call (V-cycle) or two (W-cycle: the second call solves for the
+  residual left by the first, Section 2.2), nu1 pre- and nu2
+  post-relaxations with
   red-black full Vanka, per-level damping w_l (Section 5.2 uses 0.55 /
   0.35 / 0.25 for finest/second/third levels).  The cycle preconditions
   with a zero initial guess on every level.
@@ -55,8 +57,9 @@ class CycleParams:
     def __init__(self, levels=2, alpha=0.1, damping=(0.55, 0.35, 0.25, 0.25),
                  nu1=1, nu2=1, coarse="direct", coarse_sweeps=2,
                  coarse_restart=5, coarse_maxit=10, coarse_rtol=0.0,
-                 coarse_damping=None):
+                 coarse_damping=None, calls=1):
         self.levels = levels
+        self.calls = calls
         self.alpha = alpha
         self.damping = tuple(damping)
         self.nu1, self.nu2 = nu1, nu2
@@ -135,7 +138,10 @@ class Hierarchy:
         for _ in range(self.p.nu1):
             x = sm.sweep_rb(x, b, w)
         r = b - self.A[l] @ x
-        e = self.vcycle(self.R[l] @ r, l + 1)
+        rc = self.R[l] @ r
+        e = self.vcycle(rc, l + 1)
+        if self.p.calls == 2 and l + 1 < len(self.levels) - 1:
+            e = e + self.vcycle(rc - self.A[l + 1] @ e, l + 1)
         x = x + self.P[l] @ e
         for _ in range(self.p.nu2):
             x = sm.sweep_rb(x, b, w)

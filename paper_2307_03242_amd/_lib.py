@@ -26,6 +26,7 @@ class Desc(ctypes.Structure):
         ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
         ("abl_width", ctypes.c_double), ("abl_amp", ctypes.c_double),
         ("levels", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+        ("cycle_calls", ctypes.c_int),
         ("damping", ctypes.c_double * 8),
         ("coarse_mode", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
         ("coarse_restart", ctypes.c_int), ("coarse_maxit", ctypes.c_int),

@@ -35,7 +35,7 @@ class Problem:
 
     def __init__(self, lam, mu, rho, h=1.0, omega=1.0, gamma=0.01, alpha=0.3,
                  beta=2.0 / 3.0, abl_width=0.0, abl_amp=2.0, levels=3, nu1=1,
-                 nu2=1, damping=(0.55, 0.35, 0.25), coarse_mode="krylov",
+                 nu2=1, cycle='V', damping=(0.55, 0.35, 0.25), coarse_mode="krylov",
                  coarse_sweeps=2, coarse_restart=5, coarse_maxit=10,
                  coarse_rtol=0.0, coarse_damping=0.0, precond_dtype=torch.complex128,
                  device=None):
@@ -58,6 +58,7 @@ class Problem:
         d.h, d.omega, d.gamma, d.alpha, d.beta = h, omega, gamma, alpha, beta
         d.abl_width, d.abl_amp = abl_width, abl_amp
         d.levels, d.nu1, d.nu2 = levels, nu1, nu2
+        d.cycle_calls = {'V': 1, 'W': 2}[cycle]
         damping = list(damping)
         while len(damping) < 8:
             damping.append(damping[-1])

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <complex>
@@ -88,6 +89,8 @@ struct elh_handle {
   DevBuf part, dots, coef, tmpvec;
   double* hdots = nullptr;  // pinned host mirror
   double* hcoef = nullptr;
+  int generic_stencil = 0;  // ELH_STENCIL=generic selects the reference-structured kernel
+  int zchunk = 32;          // x_3 planes per workgroup of the tiled stencil (ELH_ZCHUNK)
   int ok = 0;
 };
 
@@ -136,6 +139,7 @@ static int check_desc(const elh_desc* d) {
   if (!(d->h > 0)) return fail(ELH_ERR_ARG, "h must be positive");
   if (!(d->beta > 0 && d->beta <= 1)) return fail(ELH_ERR_ARG, "beta must be in (0,1]");
   if (d->nu1 < 0 || d->nu2 < 0) return fail(ELH_ERR_ARG, "nu1/nu2 must be >= 0");
+  if (d->cycle_calls != 1 && d->cycle_calls != 2) return fail(ELH_ERR_ARG, "cycle_calls must be 1 (V) or 2 (W)");
   if (d->coarse_mode < 0 || d->coarse_mode > 2) return fail(ELH_ERR_ARG, "bad coarse_mode");
   if (d->coarse_mode == ELH_COARSE_DENSE) return fail(ELH_ERR_ARG, "ELH_COARSE_DENSE is not available in this build");
   if (d->coarse_mode != ELH_COARSE_DENSE && d->coarse_sweeps < 1) return fail(ELH_ERR_ARG, "coarse_sweeps must be >= 1");
@@ -178,6 +182,12 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
   if (!lam || !mu || !rho) return fail(ELH_ERR_ARG, "media pointers must be non-NULL device pointers");
   elh_handle* H = new elh_handle();
   H->d = *desc;
+  {
+    const char* e = getenv("ELH_STENCIL");
+    H->generic_stencil = (e && strcmp(e, "generic") == 0) ? 1 : 0;
+    const char* z = getenv("ELH_ZCHUNK");
+    if (z && atoi(z) > 0) H->zchunk = atoi(z);
+  }
   H->st = (hipStream_t)stream;
   H->nlev = desc->levels;
   for (int l = 0; l < H->nlev; ++l) {
@@ -276,6 +286,8 @@ static int ensure_cycle_bufs(elh_handle* H, int prec, int nrhs) {
 // ---------------------------------------------------------------------------
 template <typename T>
 static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs) {
+  if (H->d.dim == 3 && !adj && !H->generic_stencil)
+    return launch_apply3d_tiled<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
   return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);
 }
 
@@ -561,6 +573,17 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
   }
   CHK(launch_restrict<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, r, C.b[prec].p, nrhs, H->st));
   CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
+  if (H->d.cycle_calls == 2 && l + 1 < H->nlev - 1) {
+    // W-cycle: second coarse cycle on the coarse residual, added to the first
+    CHK(op_apply<T>(H, l + 1, true, adj, C.x[prec].p, C.b[prec].p, C.r[prec].p, nrhs));
+    CHK((launch_scale_copy<cx<T>, cx<T>>(nullptr, C.r[prec].p, C.vs, C.b[prec].p, C.vs, C.vs, nrhs, H->st)));
+    CHK((launch_scale_copy<cx<T>, cx<T>>(nullptr, C.x[prec].p, C.vs, L.r[prec].p, C.vs, C.vs, nrhs, H->st)));
+    CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
+    std::vector<zd> one(nrhs, zd(1, 0));
+    CHK(push_coef(H, one));
+    CHK((launch_multiaxpy<cx<T>, cx<T>>(1, (const double*)H->coef.p, L.r[prec].p, 0, C.vs, C.x[prec].p, C.vs, C.vs,
+                                        nrhs, H->st)));
+  }
   CHK(launch_prolong_add<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, C.x[prec].p, x, nrhs, H->st));
   for (int s = 0; s < H->d.nu2; ++s) {
     CHK(op_relax<T>(H, l, adj, 0, b, x, nrhs, false));

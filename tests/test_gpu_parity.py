@@ -31,7 +31,7 @@ def _params(shape, levels=3, alpha=0.3, seed=3, abl=None, coarse="relax", beta=2
                 abl_amp=2.0, levels=levels, damping=(0.55, 0.35, 0.25), coarse=coarse)
 
 
-def _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6, precond=torch.complex128):
+def _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6, precond=torch.complex128, cycle="V"):
     from paper_2307_03242_amd import Problem
     m = P["media"]
     return Problem(torch.from_numpy(m["lam"]), torch.from_numpy(m["mu"]), torch.from_numpy(m["rho"]),
@@ -39,7 +39,7 @@ def _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6, precond=torch.comple
                    abl_width=P["abl_width"], abl_amp=P["abl_amp"], levels=P["levels"],
                    damping=P["damping"], coarse_mode=P["coarse"], coarse_sweeps=coarse_sweeps,
                    coarse_restart=5, coarse_maxit=coarse_maxit, coarse_rtol=0.0,
-                   precond_dtype=precond)
+                   precond_dtype=precond, cycle=cycle)
 
 
 def _oracle_levels(P, shape):
@@ -172,6 +172,20 @@ def test_vcycle_f64(shape, levels, coarse):
                        coarse_sweeps=2, coarse_restart=5, coarse_maxit=6, coarse_rtol=0.0)
     hier = C.Hierarchy(lv, cp)
     b = random_field(shape, 14, nrhs=2)
+    x = _host(prob.vcycle(_dev(b)))
+    ref = np.stack([hier.vcycle_storage(b[s]) for s in range(2)])
+    assert _relerr(x, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("shape,levels", [((16, 16, 24), 4), ((32, 48), 3)])
+def test_wcycle_f64(shape, levels):
+    P = _params(shape, levels=levels, coarse="krylov")
+    prob = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6, cycle="W")
+    lv = _oracle_levels(P, shape)[0]
+    cp = C.CycleParams(levels=levels, alpha=P["alpha"], damping=P["damping"], coarse="krylov",
+                       coarse_sweeps=2, coarse_restart=5, coarse_maxit=6, coarse_rtol=0.0, calls=2)
+    hier = C.Hierarchy(lv, cp)
+    b = random_field(shape, 17, nrhs=2)
     x = _host(prob.vcycle(_dev(b)))
     ref = np.stack([hier.vcycle_storage(b[s]) for s in range(2)])
     assert _relerr(x, ref) <= 1e-11
