@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=64, help="oracle sample grid (cells per axis)")
-    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-iters", type=int, default=40)
     return ap.parse_args()
 
 

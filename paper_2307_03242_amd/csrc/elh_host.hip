@@ -286,7 +286,10 @@ static int ensure_cycle_bufs(elh_handle* H, int prec, int nrhs) {
 // ---------------------------------------------------------------------------
 template <typename T>
 static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs) {
-  if (H->d.dim == 3 && !adj && !H->generic_stencil)
+  // the tiled kernel marches x_3 columns: it pays off once a level has
+  // enough columns to fill the chip; small coarse levels use one thread per cell
+  const int64_t small = sizeof(T) == 4 ? 48 * 48 * 48 : 24 * 24 * 24;
+  if (H->d.dim == 3 && !adj && !H->generic_stencil && H->lv[l].fs >= small)
     return launch_apply3d_tiled<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
   return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);
 }

@@ -425,14 +425,20 @@ __global__ void __launch_bounds__(RED_THREADS) k_multidot(int m, const TV* __res
   }
 }
 
-__global__ void k_reduce_parts(int m2, int nblocks, const double* __restrict__ part, double* __restrict__ out) {
-  // one thread per (rhs, entry); fixed summation order over blocks
-  const int s = blockIdx.x;
-  const int e = threadIdx.x;
-  if (e >= m2) return;
+__global__ void __launch_bounds__(256) k_reduce_parts(int m2, int nblocks, const double* __restrict__ part,
+                                                      double* __restrict__ out) {
+  // one workgroup per (entry, rhs): strided partial sums, then a fixed tree
+  const int e = blockIdx.x, s = blockIdx.y;
   double acc = 0.0;
-  for (int b = 0; b < nblocks; ++b) acc += part[((int64_t)s * nblocks + b) * m2 + e];
-  out[(int64_t)s * m2 + e] = acc;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[((int64_t)s * nblocks + b) * m2 + e];
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(int64_t)s * m2 + e] = red[0];
 }
 
 template <typename TV, typename TW>
@@ -443,7 +449,7 @@ int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_r
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL((k_multidot<TV, TW>), dim3(nb, nrhs), dim3(RED_THREADS), 0, st, m, (const TV*)V, vstride_vec,
                      vstride_rhs, (const TW*)w, wstride_rhs, len, part);
-  hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(64), 0, st, 2 * m, nb, part, out);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(2 * m, nrhs), dim3(256), 0, st, 2 * m, nb, part, out);
   return (int)hipGetLastError();
 }
 template int launch_multidot<cx<double>, cx<double>>(int, const void*, int64_t, int64_t, const void*, int64_t,

@@ -16,8 +16,8 @@
 // write no output, so the workgroup produces 62 x 4 outputs per plane.
 // Along x_3 every column keeps rolling register windows (u_k at three
 // planes, Y_k3, rho-weighted u_k for the spread mass, averaged mu);
-// neighbours in the plane come from LDS, one displacement component at a
-// time to keep the LDS footprint small.  Tiles are numbered so that the
+// neighbours in the plane come from LDS; each of the three barrier-separated
+// phases of a plane handles all displacement components.  Tiles are numbered so that the
 // workgroups of one XCD (blockIdx mod 8) sweep a contiguous block of tiles
 // and share halo columns in their L2.
 #include "elh_device.h"
@@ -31,12 +31,12 @@ constexpr int ST_OX = ST_TX - 2;      // outputs along x_1
 constexpr int ST_OY = ST_TY - 2;      // outputs along x_2
 
 template <typename T> struct Tile3 {
-  cx<T> R[ST_TY][ST_TX];    // raw u_k(t+1)
-  cx<T> Z[ST_TY][ST_TX];    // A_3 u_k(t)
-  cx<T> B1[ST_TY][ST_TX];   // A_1 u_k(t+1)
-  cx<T> Y1[ST_TY][ST_TX];   // Y_k1(t)
-  cx<T> Y2[ST_TY][ST_TX];   // Y_k2(t)
-  cx<T> W[ST_TY][ST_TX];    // rho_f u_k (t)
+  cx<T> R[3][ST_TY][ST_TX];    // raw u_k(t+1)
+  cx<T> Z[3][ST_TY][ST_TX];    // A_3 u_k(t)
+  cx<T> B1[3][ST_TY][ST_TX];   // A_1 u_k(t+1)
+  cx<T> Y1[3][ST_TY][ST_TX];   // Y_k1(t)
+  cx<T> Y2[3][ST_TY][ST_TX];   // Y_k2(t)
+  cx<T> W[3][ST_TY][ST_TX];    // rho_f u_k (t)
   cx<T> P[ST_TY][ST_TX];    // p(t)
   T Mn[ST_TY][ST_TX];       // mu(t+1)
   T Rn[ST_TY][ST_TX];       // rho(t+1)
@@ -46,25 +46,28 @@ template <typename T> struct Tile3 {
   T MZ[ST_TY][ST_TX];       // mean of mu over x_3 pairs (t)
 };
 
+// Workgroup barrier for LDS hand-off only: wait for this wave's LDS
+// operations (lgkmcnt = 0, vmcnt and expcnt left at their maxima) and meet
+// at s_barrier.  Unlike __syncthreads() it does not drain the global loads
+// that prefetch the next x_3 plane, so they stay in flight across phases.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> ldu(const cx<T>* __restrict__ f, int64_t fs, int64_t idx, bool ok) {
   return ok ? f[idx] : czero<T>();
 }
 
+// One axis of the absorbing-layer profile: amp * (delta/width)^2 with delta
+// the distance into the layer at physical coordinate xp along an axis of
+// physical length len (zero in the interior).
 template <typename T>
-__device__ __forceinline__ T absorb(const LevelArgs<T>& L, T x0, T x1, T x2) {
-  if (L.abl_w <= T(0) || L.abl_amp == T(0)) return T(0);
-  T xs[3] = {x0, x1, x2};
-  T s = T(0);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    T len = L.n[a] * L.h;
-    T d = (L.abl_w - xs[a] > T(0) ? L.abl_w - xs[a] : T(0)) +
-          (xs[a] - (len - L.abl_w) > T(0) ? xs[a] - (len - L.abl_w) : T(0));
-    T r = d / L.abl_w;
-    s += r * r;
-  }
-  return L.abl_amp * s;
+__device__ __forceinline__ T absorb_axis(T xp, T len, T w, T iw, T amp) {
+  T d = (w - xp > T(0) ? w - xp : T(0)) + (xp - (len - w) > T(0) ? xp - (len - w) : T(0));
+  T r = d * iw;
+  return amp * r * r;
 }
 
 template <typename T, bool RESID>
@@ -101,18 +104,38 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
   const T beta = L.beta, omb = T(1) - L.beta, q = T(0.25);
   const T ih = L.ih, ih2 = L.ih * L.ih;
   const T cn = omb / T(6);
-  // zero-padded / boundary-masked load of u_k at plane z
-  auto load_u = [&](int k, int z) -> cx<T> {
+  // absorbing layer: gamma~ at a face = gamma (+alpha) + sum over axes of a
+  // one-axis profile; the x_1 and x_2 parts are fixed along the x_3 march
+  const bool has_abl = L.abl_w > T(0) && L.abl_amp != T(0);
+  const T abl_iw = has_abl ? T(1) / L.abl_w : T(0);
+  const T len1 = n1 * L.h, len2 = n2 * L.h, len3 = n3 * L.h;
+  T g1f = L.gam, g2f = L.gam, g3f = L.gam;  // constant parts for u_1, u_2, u_3 faces
+  if (has_abl) {
+    const T a1c = absorb_axis<T>((T(c1) + T(0.5)) * L.h, len1, L.abl_w, abl_iw, L.abl_amp);
+    const T a1f = absorb_axis<T>(T(c1) * L.h, len1, L.abl_w, abl_iw, L.abl_amp);
+    const T a2c = absorb_axis<T>((T(c2) + T(0.5)) * L.h, len2, L.abl_w, abl_iw, L.abl_amp);
+    const T a2f = absorb_axis<T>(T(c2) * L.h, len2, L.abl_w, abl_iw, L.abl_amp);
+    g1f += a1f + a2c;
+    g2f += a1c + a2f;
+    g3f += a1c + a2c;
+  }
+  // Loads always read a valid (clamped) address; whether the value is a
+  // real unknown (inside the grid, not a boundary face) is a separate mask
+  // applied when the value enters its register window.  A masked load would
+  // be a branch + select that makes the wave wait for the prefetch at once.
+  auto u_ok = [&](int k, int z) -> bool {
     bool ok = inplane && z >= 0 && z < n3;
     if (k == 0) ok = ok && c1 > 0;
     if (k == 1) ok = ok && c2 > 0;
     if (k == 2) ok = ok && z > 0;
-    return ldu<T>(xs + k * fs, fs, (int64_t)z * plane + col, ok);
+    return ok;
   };
-  auto load_p = [&](int z) -> cx<T> {
-    bool ok = inplane && z >= 0 && z < n3;
-    return ldu<T>(xs + 3 * fs, fs, (int64_t)z * plane + col, ok);
+  auto load_raw = [&](int f, int z) -> cx<T> {
+    int zz = min(max(z, 0), n3 - 1);
+    return xs[f * fs + (int64_t)zz * plane + col];
   };
+  auto load_u = [&](int k, int z) -> cx<T> { return u_ok(k, z) ? load_raw(k, z) : czero<T>(); };
+  auto load_p = [&](int z) -> cx<T> { return (inplane && z >= 0 && z < n3) ? load_raw(3, z) : czero<T>(); };
   auto load_m = [&](const T* m, int z) -> T {
     int zz = min(max(z, 0), n3 - 1);
     return m[(int64_t)zz * plane + col];
@@ -151,21 +174,27 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
   PM = czero<T>();
   KAP = load_m(L.kap, t0);
 
+#pragma unroll 3
   for (int t = t0; t < z1; ++t) {
     // loop invariant: U[k] = u_k(t-1..t+1), Y3/W/MX/MY valid at t-1, t;
     // MU = mu(t-1..t+1), RHO = rho(t), rho(t+1), P0 = p(t), PM = p(t-1)
     // prefetch plane t+2 (and p, kappa at t+1)
     cx<T> un[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) un[k] = load_u(k, t + 2);
+    for (int k = 0; k < 3; ++k) un[k] = load_raw(k, t + 2);
     const T mun = load_m(L.mu, t + 2);
     const T rhon = load_m(L.rho, t + 2);
     const T rhosn = load_side_rho(t + 2);
-    const cx<T> pn = load_p(t + 1);
+    const cx<T> pn = load_raw(3, t + 1);
     const T kapn = load_m(L.kap, t + 1);
     const bool emit = outslot && t >= z0;
+    T a3c = T(0), a3f = T(0);
+    if (has_abl) {
+      a3c = absorb_axis<T>((T(t) + T(0.5)) * L.h, len3, L.abl_w, abl_iw, L.abl_amp);
+      a3f = absorb_axis<T>(T(t) * L.h, len3, L.abl_w, abl_iw, L.abl_amp);
+    }
 
-    // phase A: media and pressure planes
+    // phase A: media, pressure, raw u_k(t+1), A_3 u_k(t), rho-weighted u_k(t)
     S.Mn[row][lane] = MU[2];
     S.Rn[row][lane] = RHO[1];
     S.P[row][lane] = P0;
@@ -174,8 +203,15 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
     S.MY[row][lane] = MY[1];
     const T MZ = T(0.5) * (MU[0] + MU[1]);
     S.MZ[row][lane] = MZ;
-    __syncthreads();
-    // phase B: face-averaged media at t+1, rho-weighted u_k(t+1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      S.R[k][row][lane] = U[k][2];
+      S.Z[k][row][lane] = q * (U[k][0] + U[k][2]) + T(0.5) * U[k][1];
+      S.W[k][row][lane] = W[k][1];
+    }
+    lds_barrier();
+    // phase B: face-averaged media and rho-weighted u_k at t+1; A_1 u(t+1),
+    // Y_k1(t) = S_1 u(t), Y_k2(t) = S_2 u(t)
     MX[2] = T(0.5) * (S.Mn[row][lm] + MU[2]);
     MY[2] = T(0.5) * (S.Mn[rm][lane] + MU[2]);
     {
@@ -186,31 +222,27 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
       W[1][2] = rf2 * U[1][2];
       W[2][2] = rf3 * U[2][2];
     }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const cx<T> Zk = S.Z[k][row][lane];
+      S.B1[k][row][lane] = q * (S.R[k][row][lm] + S.R[k][row][lp]) + T(0.5) * U[k][2];
+      S.Y1[k][row][lane] = beta * U[k][1] + omb * (q * (S.Z[k][rm][lane] + S.Z[k][rp][lane]) + T(0.5) * Zk);
+      S.Y2[k][row][lane] = beta * U[k][1] + omb * (q * (S.Z[k][row][lm] + S.Z[k][row][lp]) + T(0.5) * Zk);
+    }
+    lds_barrier();
+    // phase C: Y_k3(t+1) = S_3 u(t+1), then the rows of plane t
     cx<T> div = czero<T>();
     cx<T> out[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      // phase C: raw u_k(t+1), A_3 u_k(t), rho-weighted u_k(t)
-      const cx<T> Zk = q * (U[k][0] + U[k][2]) + T(0.5) * U[k][1];
-      S.R[row][lane] = U[k][2];
-      S.Z[row][lane] = Zk;
-      S.W[row][lane] = W[k][1];
-      __syncthreads();
-      // phase D: A_1 u(t+1), Y_k1(t) = S_1 u(t), Y_k2(t) = S_2 u(t)
-      const cx<T> b1 = q * (S.R[row][lm] + S.R[row][lp]) + T(0.5) * U[k][2];
-      const cx<T> y1 = beta * U[k][1] + omb * (q * (S.Z[rm][lane] + S.Z[rp][lane]) + T(0.5) * Zk);
-      const cx<T> y2 = beta * U[k][1] + omb * (q * (S.Z[row][lm] + S.Z[row][lp]) + T(0.5) * Zk);
-      S.B1[row][lane] = b1;
-      S.Y1[row][lane] = y1;
-      S.Y2[row][lane] = y2;
-      __syncthreads();
-      // phase E: Y_k3(t+1) = S_3 u(t+1), then the u_k row at t
-      Y3[k][2] = beta * U[k][2] + omb * (q * (S.B1[rm][lane] + S.B1[rp][lane]) + T(0.5) * b1);
+      const cx<T> b1 = S.B1[k][row][lane];
+      Y3[k][2] = beta * U[k][2] + omb * (q * (S.B1[k][rm][lane] + S.B1[k][rp][lane]) + T(0.5) * b1);
       if (emit) {
-        const cx<T> y1m = S.Y1[row][lm], y1p = S.Y1[row][lp];
-        const cx<T> y2m = S.Y2[rm][lane], y2p = S.Y2[rp][lane];
+        const cx<T> y1 = S.Y1[k][row][lane], y2 = S.Y2[k][row][lane];
+        const cx<T> y1m = S.Y1[k][row][lm], y1p = S.Y1[k][row][lp];
+        const cx<T> y2m = S.Y2[k][rm][lane], y2p = S.Y2[k][rp][lane];
         cx<T> acc;
-        T xf0, xf1, xf2;  // face position
+        T g;  // gamma~ at the output face
         if (k == 0) {
           // d/dx1 (cell fluxes), d/dx2 and d/dx3 (edge fluxes, mu averaged over x1 pairs)
           acc = ih2 * (S.M[row][lm] * (y1 - y1m) - MU[1] * (y1p - y1));
@@ -220,7 +252,7 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
           acc += ih2 * (zlo * (Y3[0][1] - Y3[0][0]) - zhi * (Y3[0][2] - Y3[0][1]));
           acc += ih * (P0 - S.P[row][lm]);
           div += ih * (y1p - y1);
-          xf0 = T(c1); xf1 = T(c2) + T(0.5); xf2 = T(t) + T(0.5);
+          g = g1f + a3c;
         } else if (k == 1) {
           acc = ih2 * (S.M[rm][lane] * (y2 - y2m) - MU[1] * (y2p - y2));
           const T mlo = T(0.5) * (S.MY[row][lm] + MY[1]), mhi = T(0.5) * (MY[1] + S.MY[row][lp]);
@@ -229,7 +261,7 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
           acc += ih2 * (zlo * (Y3[1][1] - Y3[1][0]) - zhi * (Y3[1][2] - Y3[1][1]));
           acc += ih * (P0 - S.P[rm][lane]);
           div += ih * (y2p - y2);
-          xf0 = T(c1) + T(0.5); xf1 = T(c2); xf2 = T(t) + T(0.5);
+          g = g2f + a3c;
         } else {
           acc = ih2 * (MU[0] * (Y3[2][1] - Y3[2][0]) - MU[1] * (Y3[2][2] - Y3[2][1]));
           const T xlo = T(0.5) * (S.MZ[row][lm] + MZ), xhi = T(0.5) * (MZ + S.MZ[row][lp]);
@@ -238,18 +270,18 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
           acc += ih2 * (ylo * (y2 - y2m) - yhi * (y2p - y2));
           acc += ih * (P0 - PM);
           div += ih * (Y3[2][2] - Y3[2][1]);
-          xf0 = T(c1) + T(0.5); xf1 = T(c2) + T(0.5); xf2 = T(t);
+          g = g3f + a3f;
         }
         // spread mass with the attenuation of the output face
-        const cx<T> nb = S.W[row][lm] + S.W[row][lp] + S.W[rm][lane] + S.W[rp][lane] + W[k][0] + W[k][2];
+        const cx<T> nb = S.W[k][row][lm] + S.W[k][row][lp] + S.W[k][rm][lane] + S.W[k][rp][lane] +
+                         W[k][0] + W[k][2];
         const cx<T> sm = beta * W[k][1] + cn * nb;
-        const T g = L.gam + absorb<T>(L, xf0 * L.h, xf1 * L.h, xf2 * L.h);
         const cx<T> mf = mk(L.omega2, -L.omega2 * g);
         acc -= mf * sm;
         out[k] = acc;
       }
-      __syncthreads();
     }
+    lds_barrier();
     if (emit) {
       const int64_t o = (int64_t)t * plane + (int64_t)c2 * n1 + c1;
       const bool face[3] = {c1 > 0, c2 > 0, t > 0};
@@ -266,7 +298,7 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
     // advance the windows
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      U[k][0] = U[k][1]; U[k][1] = U[k][2]; U[k][2] = un[k];
+      U[k][0] = U[k][1]; U[k][1] = U[k][2]; U[k][2] = u_ok(k, t + 2) ? un[k] : czero<T>();
       Y3[k][0] = Y3[k][1]; Y3[k][1] = Y3[k][2];
       W[k][0] = W[k][1]; W[k][1] = W[k][2];
     }
@@ -275,7 +307,7 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
     RHOS = rhosn;
     MX[0] = MX[1]; MX[1] = MX[2];
     MY[0] = MY[1]; MY[1] = MY[2];
-    PM = P0; P0 = pn;
+    PM = P0; P0 = (inplane && t + 1 < n3) ? pn : czero<T>();
     KAP = kapn;
   }
 }
@@ -286,6 +318,12 @@ int launch_apply3d_tiled(const LevelArgs<T>& L, const void* x, const void* b, vo
   const int tiles_x = (L.n[0] + ST_OX - 1) / ST_OX;
   const int tiles_y = (L.n[1] + ST_OY - 1) / ST_OY;
   if (zc <= 0) zc = 32;
+  // keep at least ~2048 workgroups in flight: shorter x_3 chunks on small grids
+  {
+    int64_t cols = (int64_t)tiles_x * tiles_y * nrhs;
+    int64_t want = (int64_t)L.n[2] * cols / 2048;
+    if (want < zc) zc = (int)(want < 4 ? 4 : want);
+  }
   if (zc > L.n[2]) zc = L.n[2];
   const int nzc = (L.n[2] + zc - 1) / zc;
   const int64_t ntiles64 = (int64_t)tiles_x * tiles_y * nzc * nrhs;
