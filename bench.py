@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--coarse", type=str, default="krylov")
     ap.add_argument("--cycle", type=str, default="W", choices=["V", "W"])
     ap.add_argument("--coarse-sweeps", type=int, default=2)
-    ap.add_argument("--coarse-maxit", type=int, default=10)
+    ap.add_argument("--coarse-maxit", type=int, default=4)
     ap.add_argument("--coarse-rtol", type=float, default=0.0)
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=400)

@@ -48,8 +48,12 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// bumped on every (re)allocation: captured graphs embed buffer addresses
+static uint64_t g_alloc_gen = 1;
+
 static int ensure(DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes) return 0;
+  ++g_alloc_gen;
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
@@ -80,6 +84,14 @@ struct KrylovWS {
   DevBuf V, Z, w, t;
 };
 
+struct GraphEntry {
+  int prec, adj, nrhs;
+  const void* in;
+  void* out;
+  uint64_t gen;
+  hipGraphExec_t exec;
+};
+
 struct elh_handle {
   elh_desc d;
   hipStream_t st;
@@ -87,6 +99,10 @@ struct elh_handle {
   LevelData lv[8];
   KrylovWS kout[2], kin[2];  // outer (level 0, f64; Z f64/f32), inner (coarsest; f64/f32)
   DevBuf part, dots, coef, tmpvec;
+  DevBuf gstate, gpart, gdots, gnrm, gcoef, gscale, ones;  // device-resident GMRES
+  hipStream_t cap = nullptr;                               // stream used only to record graphs
+  std::vector<GraphEntry> graphs;
+  int use_graphs = 1;                                      // ELH_GRAPHS=0 disables capture
   double* hdots = nullptr;  // pinned host mirror
   double* hcoef = nullptr;
   int generic_stencil = 0;  // ELH_STENCIL=generic selects the reference-structured kernel
@@ -187,6 +203,8 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
     H->generic_stencil = (e && strcmp(e, "generic") == 0) ? 1 : 0;
     const char* z = getenv("ELH_ZCHUNK");
     if (z && atoi(z) > 0) H->zchunk = atoi(z);
+    const char* g = getenv("ELH_GRAPHS");
+    if (g && strcmp(g, "0") == 0) H->use_graphs = 0;
   }
   H->st = (hipStream_t)stream;
   H->nlev = desc->levels;
@@ -213,6 +231,26 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
       ensure(H->dots, MAXRHS_KRYLOV * MAXDOT * 16) || ensure(H->coef, MAXRHS_KRYLOV * MAXDOT * 16)) {
     elh_destroy(H);
     return ELH_ERR_OOM;
+  }
+  if (ensure(H->gstate, (size_t)MAXRHS_KRYLOV * GM_STRIDE * 8) ||
+      ensure(H->gpart, (size_t)MAXRHS_KRYLOV * 512 * MAXDOT * 2 * 8) ||
+      ensure(H->gdots, MAXRHS_KRYLOV * MAXDOT * 16) || ensure(H->gnrm, MAXRHS_KRYLOV * 16) ||
+      ensure(H->gcoef, MAXRHS_KRYLOV * MAXDOT * 16) || ensure(H->gscale, MAXRHS_KRYLOV * 16) ||
+      ensure(H->ones, MAXRHS_KRYLOV * 16)) {
+    elh_destroy(H);
+    return ELH_ERR_OOM;
+  }
+  {
+    std::vector<double> one(2 * MAXRHS_KRYLOV, 0.0);
+    for (int i = 0; i < MAXRHS_KRYLOV; ++i) one[2 * i] = 1.0;
+    if (hipMemcpy(H->ones.p, one.data(), one.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      elh_destroy(H);
+      return fail(ELH_ERR_HIP, "upload of constants failed");
+    }
+  }
+  if (hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking) != hipSuccess) {
+    elh_destroy(H);
+    return fail(ELH_ERR_HIP, "stream creation failed");
   }
   if (hipHostMalloc((void**)&H->hdots, MAXRHS_KRYLOV * MAXDOT * 16, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&H->hcoef, MAXRHS_KRYLOV * MAXDOT * 16, hipHostMallocDefault) != hipSuccess) {
@@ -250,6 +288,11 @@ extern "C" int elh_destroy(elh_handle* H) {
     for (auto* w : ws) { release(w->V); release(w->Z); release(w->w); release(w->t); }
   }
   release(H->part); release(H->dots); release(H->coef); release(H->tmpvec);
+  release(H->gstate); release(H->gpart); release(H->gdots); release(H->gnrm); release(H->gcoef);
+  release(H->gscale); release(H->ones);
+  for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
+  H->graphs.clear();
+  if (H->cap) (void)hipStreamDestroy(H->cap);
   if (H->hdots) (void)hipHostFree(H->hdots);
   if (H->hcoef) (void)hipHostFree(H->hcoef);
   delete H;
@@ -534,6 +577,54 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
   return 0;
 }
 
+// Fixed-budget restarted GMRES with all bookkeeping on the device (no host
+// synchronisation, graph-capturable).  Same algorithm as gmres() with
+// rtol = 0: classical Gram-Schmidt, complex Givens, restart every m steps,
+// exactly `maxit` preconditioner applications.
+template <typename T, typename OpAZ, typename OpAR, typename OpM>
+static int gmres_device(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, OpAR AR, OpM M, const void* b,
+                        void* x, int restart, int maxit) {
+  typedef cx<T> CT;
+  const int m = restart;
+  const size_t vbytes = (size_t)nrhs * len * sizeof(CT);
+  if (ensure(ws.V, vbytes * (m + 1)) || ensure(ws.Z, vbytes * m) || ensure(ws.w, vbytes)) return ELH_ERR_OOM;
+  CT* V = (CT*)ws.V.p;
+  CT* Z = (CT*)ws.Z.p;
+  CT* w = (CT*)ws.w.p;
+  const int64_t vstr = (int64_t)nrhs * len;
+  hipStream_t st = H->st;
+  double* gst = (double*)H->gstate.p;
+  double* gpart = (double*)H->gpart.p;
+  double* gdots = (double*)H->gdots.p;
+  double* gnrm = (double*)H->gnrm.p;
+  double* gcoef = (double*)H->gcoef.p;
+  double* gscale = (double*)H->gscale.p;
+  CHK(launch_zero(x, vbytes, st));
+  CHK((launch_scale_copy<CT, CT>(nullptr, b, len, w, len, len, nrhs, st)));
+  int done = 0;
+  while (done < maxit) {
+    CHK((launch_multidot<CT, CT>(1, w, 0, len, w, len, len, nrhs, gpart, gnrm, st)));
+    CHK(launch_gm_start(nrhs, gnrm, gst, gscale, st));
+    CHK((launch_scale_copy<CT, CT>(gscale, w, len, V, len, len, nrhs, st)));
+    const int k = (maxit - done) < m ? (maxit - done) : m;
+    for (int j = 0; j < k; ++j) {
+      CHK(M((const void*)(V + j * vstr), (void*)(Z + j * vstr)));
+      CHK(AZ((const void*)(Z + j * vstr), (void*)w));
+      CHK((launch_multidot<CT, CT>(j + 1, V, vstr, len, w, len, len, nrhs, gpart, gdots, st)));
+      CHK(launch_gm_hcol(nrhs, j, gdots, gst, gcoef, st));
+      CHK((launch_multiaxpy<CT, CT>(j + 1, gcoef, V, vstr, len, w, len, len, nrhs, st)));
+      CHK((launch_multidot<CT, CT>(1, w, 0, len, w, len, len, nrhs, gpart, gnrm, st)));
+      CHK(launch_gm_rotate(nrhs, j, gnrm, gst, gscale, st));
+      if (j + 1 < k) CHK((launch_scale_copy<CT, CT>(gscale, w, len, V + (j + 1) * vstr, len, len, nrhs, st)));
+    }
+    CHK(launch_gm_backsolve(nrhs, k, gst, gcoef, st));
+    CHK((launch_multiaxpy<CT, CT>(k, gcoef, Z, vstr, len, x, len, len, nrhs, st)));
+    done += k;
+    if (done < maxit) CHK(AR((const void*)x, b, (void*)w));
+  }
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // coarsest solve and cycle
 // ---------------------------------------------------------------------------
@@ -549,6 +640,8 @@ static int coarse_solve(elh_handle* H, bool adj, const void* b, void* x, int nrh
   auto AZ = [&](const void* zi, void* wo) { return op_apply<T>(H, l, true, adj, zi, nullptr, wo, nrhs); };
   auto AR = [&](const void* xi, const void* bi, void* ro) { return op_apply<T>(H, l, true, adj, xi, bi, ro, nrhs); };
   auto M = [&](const void* v, void* z) { return op_sweeps_from_zero<T>(H, l, adj, v, z, nrhs, d.coarse_sweeps); };
+  if (d.coarse_rtol <= 0)
+    return gmres_device<T>(H, H->kin[prec], L.vs, nrhs, AZ, AR, M, b, x, d.coarse_restart, d.coarse_maxit);
   GmresStats gs;
   int rc = gmres<T, T>(H, H->kin[prec], L.vs, nrhs, AZ, AR, M, b, x, d.coarse_restart, d.coarse_maxit,
                        d.coarse_rtol, gs);
@@ -582,9 +675,7 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
     CHK((launch_scale_copy<cx<T>, cx<T>>(nullptr, C.r[prec].p, C.vs, C.b[prec].p, C.vs, C.vs, nrhs, H->st)));
     CHK((launch_scale_copy<cx<T>, cx<T>>(nullptr, C.x[prec].p, C.vs, L.r[prec].p, C.vs, C.vs, nrhs, H->st)));
     CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
-    std::vector<zd> one(nrhs, zd(1, 0));
-    CHK(push_coef(H, one));
-    CHK((launch_multiaxpy<cx<T>, cx<T>>(1, (const double*)H->coef.p, L.r[prec].p, 0, C.vs, C.x[prec].p, C.vs, C.vs,
+    CHK((launch_multiaxpy<cx<T>, cx<T>>(1, (const double*)H->ones.p, L.r[prec].p, 0, C.vs, C.x[prec].p, C.vs, C.vs,
                                         nrhs, H->st)));
   }
   CHK(launch_prolong_add<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, C.x[prec].p, x, nrhs, H->st));
@@ -593,6 +684,58 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
     CHK(op_relax<T>(H, l, adj, 1, b, x, nrhs, false));
   }
   return 0;
+}
+
+// Run `fn` (which enqueues on H->st) through a cached hipGraph: recorded
+// once on a private stream, then replayed on the handle's stream.  Only
+// sequences with no host synchronisation are captured (the cycle with a
+// fixed-budget coarse solve).
+template <typename Fn>
+static int run_graph(elh_handle* H, int prec, int adj, int nrhs, const void* in, void* out, Fn fn) {
+  for (size_t i = 0; i < H->graphs.size(); ++i) {
+    GraphEntry& g = H->graphs[i];
+    if (g.prec == prec && g.adj == adj && g.nrhs == nrhs && g.in == in && g.out == out) {
+      if (g.gen == g_alloc_gen) {
+        HIPCHK(hipGraphLaunch(g.exec, H->st));
+        return 0;
+      }
+      (void)hipGraphExecDestroy(g.exec);
+      H->graphs.erase(H->graphs.begin() + i);
+      break;
+    }
+  }
+  // the first (eager) run also performs any lazy allocation, so the recorded
+  // addresses are final
+  CHK(fn());
+  const uint64_t gen = g_alloc_gen;
+  hipStream_t saved = H->st;
+  H->st = H->cap;
+  hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    H->st = saved;
+    return fail(ELH_ERR_HIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+  }
+  int rc = fn();
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(H->cap, &graph);
+  H->st = saved;
+  if (rc != 0 || e != hipSuccess || gen != g_alloc_gen) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != 0) return rc > 0 ? fail(ELH_ERR_HIP, "launch failed during graph capture") : rc;
+    if (e != hipSuccess) return fail(ELH_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    return 0;  // allocation changed while recording: keep running eagerly
+  }
+  GraphEntry g;
+  g.prec = prec; g.adj = adj; g.nrhs = nrhs; g.in = in; g.out = out; g.gen = gen;
+  e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(ELH_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  H->graphs.push_back(g);
+  return 0;
+}
+
+static bool graphs_ok(const elh_handle* H) {
+  return H->use_graphs && !(H->d.coarse_mode == ELH_COARSE_KRYLOV && H->d.coarse_rtol > 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,7 +860,10 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
   };
   if (pprec == 0) {
     auto AZ = [&](const void* zi, void* wo) { return op_apply<double>(H, 0, false, adj, zi, nullptr, wo, nrhs); };
-    auto M = [&](const void* v, void* z) { return cycle<double>(H, 0, adj, v, z, nrhs); };
+    auto M = [&](const void* v, void* z) {
+      auto fn = [&]() { return cycle<double>(H, 0, adj, v, z, nrhs); };
+      return graphs_ok(H) ? run_graph(H, 0, adj, nrhs, v, z, fn) : fn();
+    };
     rc = gmres<double, double>(H, H->kout[0], len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol,
                                gs);
   } else {
@@ -727,8 +873,11 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
     KrylovWS& ws = H->kout[1];
     if (ensure(ws.t, (size_t)nrhs * len * 16)) return ELH_ERR_OOM;
     auto M = [&](const void* v, void* z) {
-      CHK((launch_scale_copy<cx<double>, cx<float>>(nullptr, v, len, L0.b[1].p, len, len, nrhs, H->st)));
-      return cycle<float>(H, 0, adj, L0.b[1].p, z, nrhs);
+      auto fn = [&]() {
+        CHK((launch_scale_copy<cx<double>, cx<float>>(nullptr, v, len, L0.b[1].p, len, len, nrhs, H->st)));
+        return cycle<float>(H, 0, adj, L0.b[1].p, z, nrhs);
+      };
+      return graphs_ok(H) ? run_graph(H, 1, adj, nrhs, v, z, fn) : fn();
     };
     auto AZ = [&](const void* zi, void* wo) {
       CHK((launch_scale_copy<cx<float>, cx<double>>(nullptr, zi, len, ws.t.p, len, len, nrhs, H->st)));
@@ -762,8 +911,12 @@ extern "C" int elh_solve_adjoint(elh_handle* H, int nrhs, const void* r, void* v
 
 extern "C" int elh_gradient(elh_handle* H, int nrhs, const void* u, const void* v, double* g_lam, double* g_mu,
                             double* g_rho) {
-  (void)H; (void)nrhs; (void)u; (void)v; (void)g_lam; (void)g_mu; (void)g_rho;
-  return fail(ELH_ERR_STATE, "elh_gradient is not available in this build");
+  int rc = check_common(H, 0, ELH_C128, nrhs);
+  if (rc) return rc;
+  if (!u || !v || !g_lam || !g_mu || !g_rho) return fail(ELH_ERR_ARG, "u, v and the gradients must be non-NULL");
+  // the gradient is of the unshifted forward operator
+  CHK(launch_gradient(largs<double>(H, 0, false), H->d.dim, nrhs, u, v, g_lam, g_mu, g_rho, H->st));
+  return 0;
 }
 
 extern "C" const char* elh_status_string(int s) {

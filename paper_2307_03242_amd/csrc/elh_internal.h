@@ -8,6 +8,9 @@ namespace elh {
 
 constexpr int MAXDOT = 16;         // most vectors in one fused multi-dot
 constexpr int MAXRHS_KRYLOV = 64;  // right-hand sides per Krylov solve (reduction buffers)
+// per-rhs device GMRES state in doubles: H (MAXDOT x MAXDOT complex), g and
+// sines (MAXDOT complex each), cosines (MAXDOT)
+constexpr int GM_STRIDE = 2 * MAXDOT * MAXDOT + 2 * MAXDOT + 2 * MAXDOT + MAXDOT;
 
 template <typename T>
 int launch_apply(const LevelArgs<T>& L, int dim, bool adj, const void* x, const void* b, void* y, int nrhs,
@@ -37,5 +40,11 @@ template <typename TX, typename TY>
 int launch_scale_copy(const double* a, const void* x, int64_t xstride, void* y, int64_t ystride, int64_t len,
                       int nrhs, hipStream_t st);
 int launch_zero(void* p, int64_t bytes, hipStream_t st);
+int launch_gradient(const LevelArgs<double>& L, int dim, int nrhs, const void* u, const void* v, double* gl,
+                    double* gm, double* gr, hipStream_t st);
+int launch_gm_start(int nrhs, const double* nrm2, double* st, double* scale, hipStream_t s);
+int launch_gm_hcol(int nrhs, int j, const double* dots, double* st, double* coef, hipStream_t s);
+int launch_gm_rotate(int nrhs, int j, const double* nrm2, double* st, double* scale, hipStream_t s);
+int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStream_t s);
 
 }  // namespace elh

@@ -334,6 +334,109 @@ template int launch_prolong_add<float>(const LevelArgs<float>&, const LevelArgs<
                                        int, hipStream_t);
 
 // ---------------------------------------------------------------------------
+// parameter gradient  g_m(c) = - Re sum_s v_s^H (dH/dm_c) u_s  (float64)
+// ---------------------------------------------------------------------------
+// Gather form, one thread per cell, loop over sources.  H depends on
+//  * mu through A_e(mu): the x_k-derivative flux of u_k at cell c uses mu_c;
+//    a transverse flux on an edge uses the mean of the four cells around it
+//    (media clamped at the boundary, so a boundary edge counts a cell twice);
+//  * lam and mu through kappa = 1/(lam+mu): dkappa = -kappa^2;
+//  * rho through A_f(rho): the mean of the two cells beside a face.
+// For the Laplacian term the derivative of v_k^H D^T diag(mu_e) D Y u_k is
+// conj(D v_k) (D Y u_k) at the flux point; for the mass term
+// - v_k^H diag(w2) S diag(rho_f) u_k it is - conj(S conj(w2) v_k) u_k at the face.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_gradient(LevelArgs<double> L, int nrhs, const cx<double>* __restrict__ u,
+                                                   const cx<double>* __restrict__ v, double* __restrict__ g_lam,
+                                                   double* __restrict__ g_mu, double* __restrict__ g_rho) {
+  typedef double T;
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= L.fs) return;
+  int c[3];
+  c[0] = (int)(cell % L.n[0]);
+  c[1] = (int)((cell / L.n[0]) % L.n[1]);
+  c[2] = (int)(cell / ((int64_t)L.n[0] * L.n[1]));
+  const T kap = L.kap[cell];
+  const T cn = (T(1) - L.beta) / T(2 * DIM);
+  T gl = 0, gm = 0, gr = 0;
+  for (int s = 0; s < nrhs; ++s) {
+    const cx<T>* us = u + (int64_t)s * L.vs;
+    const cx<T>* vs = v + (int64_t)s * L.vs;
+    const cx<T> up = us[DIM * L.fs + cell], vp = vs[DIM * L.fs + cell];
+    const T kp = kap * kap * (vp.re * up.re + vp.im * up.im);
+    gl += kp;
+    gm += kp;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      // flux of u_k along x_k at cell c
+      {
+        int j[3] = {c[0], c[1], c[2]};
+        j[k] = c[k] + 1;
+        cx<T> dv = ldf<DIM>(vs, L, k, j);
+        j[k] = c[k];
+        dv = L.ih * (dv - ldf<DIM>(vs, L, k, j));
+        cx<T> dy = spread_flux<DIM>(us, L, k, k, c[k], c);
+        gm -= dv.re * dy.re + dv.im * dy.im;
+      }
+      // transverse fluxes on the edges around cell c
+#pragma unroll
+      for (int l = 0; l < DIM; ++l) {
+        if (l == k) continue;
+        for (int f = c[k]; f <= c[k] + 1; ++f) {
+          if (f < 1 || f > L.n[k] - 1) continue;
+          for (int e = c[l]; e <= c[l] + 1; ++e) {
+            // edge (k-face f, l-face e): cells clamp(e-1), clamp(e) along l
+            T wgt = T(0.25);
+            if (e == c[l] && e - 1 < 0) wgt += T(0.25);
+            if (e == c[l] + 1 && e > L.n[l] - 1) wgt += T(0.25);
+            int t[3] = {c[0], c[1], c[2]};
+            t[k] = f;
+            int j[3] = {t[0], t[1], t[2]};
+            j[l] = e;
+            cx<T> dv = ldf<DIM>(vs, L, k, j);
+            j[l] = e - 1;
+            dv = L.ih * (dv - ldf<DIM>(vs, L, k, j));
+            cx<T> dy = spread_flux<DIM>(us, L, k, l, e, t);
+            gm -= wgt * (dv.re * dy.re + dv.im * dy.im);
+          }
+        }
+      }
+      // spread mass on the two faces of cell c normal to x_k
+      for (int f = c[k]; f <= c[k] + 1; ++f) {
+        if (f < 1 || f > L.n[k] - 1) continue;
+        int F[3] = {c[0], c[1], c[2]};
+        F[k] = f;
+        cx<T> w = L.beta * (conj(mass_factor<DIM>(L, k, F)) * vs[k * L.fs + lin<DIM>(L.n, F)]);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int sg = -1; sg <= 1; sg += 2) {
+            int Q[3] = {F[0], F[1], F[2]};
+            Q[a] += sg;
+            if (!in_grid<DIM>(L.n, Q) || Q[k] == 0) continue;
+            w += cn * (conj(mass_factor<DIM>(L, k, Q)) * vs[k * L.fs + lin<DIM>(L.n, Q)]);
+          }
+        const cx<T> uf = us[k * L.fs + lin<DIM>(L.n, F)];
+        gr += T(0.5) * (w.re * uf.re + w.im * uf.im);
+      }
+    }
+  }
+  g_lam[cell] = gl;
+  g_mu[cell] = gm;
+  g_rho[cell] = gr;
+}
+
+int launch_gradient(const LevelArgs<double>& L, int dim, int nrhs, const void* u, const void* v, double* gl,
+                    double* gm, double* gr, hipStream_t st) {
+  dim3 blk(256), grd((unsigned)((L.fs + 255) / 256));
+  if (dim == 3)
+    hipLaunchKernelGGL(k_gradient<3>, grd, blk, 0, st, L, nrhs, (const cx<double>*)u, (const cx<double>*)v, gl, gm, gr);
+  else
+    hipLaunchKernelGGL(k_gradient<2>, grd, blk, 0, st, L, nrhs, (const cx<double>*)u, (const cx<double>*)v, gl, gm, gr);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // media setup: child means, kappa, casts
 // ---------------------------------------------------------------------------
 __global__ void k_coarsen_media(int dim, int f0, int f1, int f2, const double* __restrict__ a, double* __restrict__ out) {
@@ -525,6 +628,137 @@ template int launch_scale_copy<cx<float>, cx<double>>(const double*, const void*
                                                       int, hipStream_t);
 template int launch_scale_copy<cx<float>, cx<float>>(const double*, const void*, int64_t, void*, int64_t, int64_t,
                                                      int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Device-resident GMRES bookkeeping (one thread per right-hand side): the
+// Hessenberg column, complex Givens rotations, the residual estimate and the
+// least-squares back substitution stay on the GPU, so a fixed-budget solve
+// needs no host round trip (and can be captured in a graph).
+// State layout per rhs s (doubles): see GmresDev in elh_internal.h.
+// ---------------------------------------------------------------------------
+struct zc { double re, im; };
+__device__ inline zc zmul(zc a, zc b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline zc zconj(zc a) { return {a.re, -a.im}; }
+__device__ inline double zabs(zc a) { return hypot(a.re, a.im); }
+
+__device__ inline zc* gm_H(double* st, int s, int i, int j) {  // H[i][j], i < MAXDOT, j < MAXDOT
+  return (zc*)(st + (size_t)s * GM_STRIDE) + i * MAXDOT + j;
+}
+__device__ inline zc* gm_g(double* st, int s) { return (zc*)(st + (size_t)s * GM_STRIDE + 2 * MAXDOT * MAXDOT); }
+__device__ inline zc* gm_sn(double* st, int s) { return gm_g(st, s) + MAXDOT; }
+__device__ inline double* gm_cs(double* st, int s) { return (double*)(gm_sn(st, s) + MAXDOT); }
+
+// start of a restart cycle: beta = ||r||, g = (beta, 0, ...), scale = 1/beta
+__global__ void k_gm_start(int nrhs, const double* __restrict__ nrm2, double* __restrict__ st,
+                           double* __restrict__ scale) {
+  int s = threadIdx.x;
+  if (s >= nrhs) return;
+  double beta = sqrt(nrm2[2 * s]);
+  zc* g = gm_g(st, s);
+  for (int i = 0; i < MAXDOT; ++i) g[i] = {0.0, 0.0};
+  g[0] = {beta, 0.0};
+  scale[2 * s] = beta > 0 ? 1.0 / beta : 0.0;
+  scale[2 * s + 1] = 0.0;
+}
+
+// after the dots h_i = <V_i, w>, i <= j: store column j and coef = -h
+__global__ void k_gm_hcol(int nrhs, int j, const double* __restrict__ dots, double* __restrict__ st,
+                          double* __restrict__ coef) {
+  int s = threadIdx.x;
+  if (s >= nrhs) return;
+  for (int i = 0; i <= j; ++i) {
+    zc h = {dots[(s * (j + 1) + i) * 2], dots[(s * (j + 1) + i) * 2 + 1]};
+    *gm_H(st, s, i, j) = h;
+    coef[(s * (j + 1) + i) * 2] = -h.re;
+    coef[(s * (j + 1) + i) * 2 + 1] = -h.im;
+  }
+}
+
+// after ||w||^2: subdiagonal, previous rotations, new rotation, g update,
+// scale = 1/h_{j+1,j}
+__global__ void k_gm_rotate(int nrhs, int j, const double* __restrict__ nrm2, double* __restrict__ st,
+                            double* __restrict__ scale) {
+  int s = threadIdx.x;
+  if (s >= nrhs) return;
+  double hn = sqrt(nrm2[2 * s]);
+  *gm_H(st, s, j + 1, j) = {hn, 0.0};
+  zc* sn = gm_sn(st, s);
+  double* cs = gm_cs(st, s);
+  for (int i = 0; i < j; ++i) {
+    zc a = *gm_H(st, s, i, j), b = *gm_H(st, s, i + 1, j);
+    zc t = zmul(sn[i], b);
+    zc na = {cs[i] * a.re + t.re, cs[i] * a.im + t.im};
+    zc u = zmul(zconj(sn[i]), a);
+    zc nb = {-u.re + cs[i] * b.re, -u.im + cs[i] * b.im};
+    *gm_H(st, s, i, j) = na;
+    *gm_H(st, s, i + 1, j) = nb;
+  }
+  zc a = *gm_H(st, s, j, j), b = *gm_H(st, s, j + 1, j);
+  double c;
+  zc sg;
+  double aa = zabs(a), bb = zabs(b);
+  if (bb == 0) { c = 1; sg = {0, 0}; }
+  else if (aa == 0) { c = 0; sg = {b.re / bb, -b.im / bb}; }
+  else {
+    double den = hypot(aa, bb);
+    c = aa / den;
+    zc ph = {a.re / aa, a.im / aa};
+    sg = zmul(ph, zc{b.re / den, -b.im / den});
+  }
+  cs[j] = c;
+  sn[j] = sg;
+  zc t = zmul(sg, b);
+  *gm_H(st, s, j, j) = {c * a.re + t.re, c * a.im + t.im};
+  *gm_H(st, s, j + 1, j) = {0, 0};
+  zc* g = gm_g(st, s);
+  zc gj = g[j];
+  zc u = zmul(zconj(sg), gj);
+  g[j + 1] = {-u.re, -u.im};
+  g[j] = {c * gj.re, c * gj.im};
+  scale[2 * s] = hn > 0 ? 1.0 / hn : 0.0;
+  scale[2 * s + 1] = 0.0;
+}
+
+// y = R^{-1} g over k columns (zero where the triangle is singular)
+__global__ void k_gm_backsolve(int nrhs, int k, const double* __restrict__ st, double* __restrict__ coef) {
+  int s = threadIdx.x;
+  if (s >= nrhs) return;
+  double* stw = const_cast<double*>(st);
+  const zc* g = gm_g(stw, s);
+  zc y[MAXDOT];
+  for (int i = k - 1; i >= 0; --i) {
+    zc acc = g[i];
+    for (int q = i + 1; q < k; ++q) {
+      zc t = zmul(*gm_H(stw, s, i, q), y[q]);
+      acc.re -= t.re;
+      acc.im -= t.im;
+    }
+    zc d = *gm_H(stw, s, i, i);
+    double dd = d.re * d.re + d.im * d.im;
+    y[i] = dd > 0 ? zc{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd} : zc{0, 0};
+  }
+  for (int i = 0; i < k; ++i) {
+    coef[(s * k + i) * 2] = y[i].re;
+    coef[(s * k + i) * 2 + 1] = y[i].im;
+  }
+}
+
+int launch_gm_start(int nrhs, const double* nrm2, double* st, double* scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_start, dim3(1), dim3(64), 0, s, nrhs, nrm2, st, scale);
+  return (int)hipGetLastError();
+}
+int launch_gm_hcol(int nrhs, int j, const double* dots, double* st, double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_hcol, dim3(1), dim3(64), 0, s, nrhs, j, dots, st, coef);
+  return (int)hipGetLastError();
+}
+int launch_gm_rotate(int nrhs, int j, const double* nrm2, double* st, double* scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_rotate, dim3(1), dim3(64), 0, s, nrhs, j, nrm2, st, scale);
+  return (int)hipGetLastError();
+}
+int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_backsolve, dim3(1), dim3(64), 0, s, nrhs, k, st, coef);
+  return (int)hipGetLastError();
+}
 
 __global__ void k_fill_zero(uint2* p, int64_t n8) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -270,3 +270,50 @@ def test_argument_errors_on_gpu():
     assert prob.lib.elh_apply(prob.handle, 0, 0, 2, 1, x.data_ptr(), x.data_ptr()) == -1
     with pytest.raises(ValueError):
         prob.apply(_dev(random_field((8, 8, 6), 1)))
+
+
+@pytest.mark.parametrize("precond", [torch.complex128, torch.complex64])
+def test_graph_replays_match_eager(precond):
+    """The preconditioner cycle (device-resident coarse GMRES) is recorded
+    once into a hipGraph and replayed; every replayed solve, with eager work
+    and synchronisations in between, equals the eagerly launched solve."""
+    import os
+    shape = (16, 16, 24)
+    P = _params(shape, levels=3, coarse="krylov")
+    old = os.environ.get("ELH_GRAPHS")
+    os.environ["ELH_GRAPHS"] = "0"
+    try:
+        eager = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=7, precond=precond)
+    finally:
+        if old is None:
+            del os.environ["ELH_GRAPHS"]
+        else:
+            os.environ["ELH_GRAPHS"] = old
+    graphed = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=7, precond=precond)
+    q = _dev(np.stack([point_source(shape), random_field(shape, 41)]))
+    ue, infoe, _ = eager.solve(q, rtol=1e-8, maxit=200)
+    ue = _host(ue)
+    x = _dev(random_field(shape, 42))
+    for rep in range(3):
+        ug, infog, _ = graphed.solve(q, rtol=1e-8, maxit=200)
+        torch.cuda.synchronize()
+        assert [i["iters"] for i in infog] == [i["iters"] for i in infoe]
+        assert np.array_equal(_host(ug), ue), rep
+        graphed.apply(x)            # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_device_coarse_gmres_matches_oracle_krylov():
+    """fixed-budget coarsest solve (device-resident GMRES + Vanka sweeps)
+    against the oracle's GMRES with the same budget"""
+    shape = (16, 16, 16)
+    P = _params(shape, levels=2, coarse="krylov")
+    prob = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=12)
+    lv = _oracle_levels(P, shape)[0]
+    hier = C.Hierarchy(lv, C.CycleParams(levels=2, alpha=P["alpha"], damping=P["damping"], coarse="krylov",
+                                         coarse_sweeps=2, coarse_restart=5, coarse_maxit=12, coarse_rtol=0.0))
+    lvc = hier.levels[-1]
+    b = random_field(lvc.np_shape, 43, nrhs=3)
+    x = _host(prob.coarse_solve(_dev(b)))
+    ref = np.stack([G.unpack(lvc, hier.coarse_solve(G.pack(lvc, b[s]))) for s in range(3)])
+    assert _relerr(x, ref) <= 1e-10
