@@ -52,6 +52,7 @@ template <typename T> struct LevelArgs {
   T omega2;          // omega^2
   T gam;             // gamma (+ alpha for the shifted operator)
   T abl_w, abl_amp;  // absorbing layer (physical width, amplitude)
+  T abl_iw;          // 1 / abl_w (0 when there is no layer)
   const T* mu;       // cell media (fs each)
   const T* rho;
   const T* kap;      // 1/(lam+mu)
@@ -95,7 +96,7 @@ __device__ __forceinline__ T abl_gamma(const LevelArgs<T>& L, const T* xp) {
     T len = L.n[a] * L.h;
     T d = (L.abl_w - xp[a] > T(0) ? L.abl_w - xp[a] : T(0)) +
           (xp[a] - (len - L.abl_w) > T(0) ? xp[a] - (len - L.abl_w) : T(0));
-    T r = d / L.abl_w;
+    T r = d * L.abl_iw;
     s += r * r;
   }
   return L.abl_amp * s;

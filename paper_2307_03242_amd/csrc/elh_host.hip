@@ -129,6 +129,7 @@ static LevelArgs<T> largs(const elh_handle* H, int l, bool shifted) {
   a.gam = (T)(H->d.gamma + (shifted ? H->d.alpha : 0.0));
   a.abl_w = (T)H->d.abl_width;
   a.abl_amp = (T)H->d.abl_amp;
+  a.abl_iw = H->d.abl_width > 0 ? (T)(1.0 / H->d.abl_width) : (T)0;
   if (sizeof(T) == 8) {
     a.mu = (const T*)L.mu.p;
     a.rho = (const T*)L.rho.p;
@@ -331,7 +332,7 @@ template <typename T>
 static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs) {
   // the tiled kernel marches x_3 columns: it pays off once a level has
   // enough columns to fill the chip; small coarse levels use one thread per cell
-  const int64_t small = sizeof(T) == 4 ? 48 * 48 * 48 : 24 * 24 * 24;
+  const int64_t small = 24 * 24 * 24;
   if (H->d.dim == 3 && !adj && !H->generic_stencil && H->lv[l].fs >= small)
     return launch_apply3d_tiled<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
   return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);

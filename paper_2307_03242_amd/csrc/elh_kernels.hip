@@ -125,14 +125,21 @@ __device__ void vanka_block(const LevelArgs<T>& L, int k, const int* c, cx<T>* B
 template <int DIM, bool ADJ, typename T>
 __global__ void __launch_bounds__(256) k_vanka(LevelArgs<T> L, const cx<T>* __restrict__ r, cx<T>* __restrict__ x,
                                                 int colour, T w, int nrhs) {
-  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // one thread per cell of the active colour: thread i takes the i-th
+  // such cell of its x_1 line (lines hold ceil/floor(n_1/2) of them)
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  if (cell >= L.fs || s >= nrhs) return;
+  const int half = (L.n[0] + 1) / 2;
+  const int64_t lines = L.fs / L.n[0];
+  if (id >= lines * half || s >= nrhs) return;
+  const int64_t line = id / half;
   int c[3];
-  c[0] = (int)(cell % L.n[0]);
-  c[1] = (int)((cell / L.n[0]) % L.n[1]);
-  c[2] = (int)(cell / ((int64_t)L.n[0] * L.n[1]));
-  if (((c[0] + c[1] + c[2]) & 1) != colour) return;
+  c[1] = (int)(line % L.n[1]);
+  c[2] = (int)(line / L.n[1]);
+  const int par = (colour + c[1] + c[2]) & 1;  // parity of c_1 on this line
+  c[0] = 2 * (int)(id % half) + par;
+  if (c[0] >= L.n[0]) return;
+  const int64_t cell = line * L.n[0] + c[0];
   const cx<T>* rs = r + s * L.vs;
   cx<T>* xs = x + s * L.vs;
   const T s0 = L.beta + (T(1) - L.beta) / T(DIM == 3 ? 4 : 2);
@@ -168,8 +175,10 @@ __global__ void __launch_bounds__(256) k_vanka(LevelArgs<T> L, const cx<T>* __re
     cx<T> rk[2];
     rk[0] = ok[k][0] ? rs[idx[k][0]] : czero<T>();
     rk[1] = ok[k][1] ? rs[idx[k][1]] : czero<T>();
-    cx<T> det = B[0] * B[3] - B[1] * B[2];
-    cx<T> inv00 = cdiv(B[3], det), inv01 = cdiv(-B[1], det), inv10 = cdiv(-B[2], det), inv11 = cdiv(B[0], det);
+    const cx<T> det = B[0] * B[3] - B[1] * B[2];
+    const T id2 = T(1) / abs2(det);
+    const cx<T> rdet = mk(det.re * id2, -det.im * id2);  // 1/det
+    const cx<T> inv00 = B[3] * rdet, inv01 = -(B[1] * rdet), inv10 = -(B[2] * rdet), inv11 = B[0] * rdet;
     yr[k][0] = inv00 * rk[0] + inv01 * rk[1];
     yr[k][1] = inv10 * rk[0] + inv11 * rk[1];
     yg[k][0] = inv00 * g[0] + inv01 * g[1];
@@ -177,7 +186,8 @@ __global__ void __launch_bounds__(256) k_vanka(LevelArgs<T> L, const cx<T>* __re
     rp -= d[0] * yr[k][0] + d[1] * yr[k][1];
     schur -= d[0] * yg[k][0] + d[1] * yg[k][1];
   }
-  cx<T> dp = cdiv(rp, schur);
+  const T is2 = T(1) / abs2(schur);
+  cx<T> dp = rp * mk(schur.re * is2, -schur.im * is2);
   xs[DIM * L.fs + cell] += w * dp;
 #pragma unroll
   for (int k = 0; k < DIM; ++k)
@@ -189,7 +199,8 @@ __global__ void __launch_bounds__(256) k_vanka(LevelArgs<T> L, const cx<T>* __re
 template <typename T>
 int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* x, int colour, double w, int nrhs,
                  hipStream_t st) {
-  dim3 blk(256), grd((unsigned)((L.fs + 255) / 256), nrhs);
+  const int64_t work = (L.fs / L.n[0]) * ((L.n[0] + 1) / 2);
+  dim3 blk(256), grd((unsigned)((work + 255) / 256), nrhs);
   const cx<T>* rp = (const cx<T>*)r;
   cx<T>* xp = (cx<T>*)x;
   if (dim == 3) {

@@ -107,7 +107,7 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
   // absorbing layer: gamma~ at a face = gamma (+alpha) + sum over axes of a
   // one-axis profile; the x_1 and x_2 parts are fixed along the x_3 march
   const bool has_abl = L.abl_w > T(0) && L.abl_amp != T(0);
-  const T abl_iw = has_abl ? T(1) / L.abl_w : T(0);
+  const T abl_iw = L.abl_iw;
   const T len1 = n1 * L.h, len2 = n2 * L.h, len3 = n3 * L.h;
   T g1f = L.gam, g2f = L.gam, g3f = L.gam;  // constant parts for u_1, u_2, u_3 faces
   if (has_abl) {
@@ -188,6 +188,14 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
     const cx<T> pn = load_raw(3, t + 1);
     const T kapn = load_m(L.kap, t + 1);
     const bool emit = outslot && t >= z0;
+    // right-hand side of plane t for the residual, fetched with the plane
+    // prefetch so it is in flight during the phases below
+    cx<T> bq[4];
+    if (RESID) {
+      const int64_t o = (int64_t)min(max(t, 0), n3 - 1) * plane + col;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) bq[f] = bs[f * fs + o];
+    }
     T a3c = T(0), a3f = T(0);
     if (has_abl) {
       a3c = absorb_axis<T>((T(t) + T(0.5)) * L.h, len3, L.abl_w, abl_iw, L.abl_amp);
@@ -288,11 +296,11 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         cx<T> v = face[k] ? out[k] : czero<T>();
-        if (RESID && face[k]) v = bs[k * fs + o] - v;
+        if (RESID && face[k]) v = bq[k] - v;
         ys[k * fs + o] = v;
       }
       cx<T> vp = div + KAP * P0;
-      if (RESID) vp = bs[3 * fs + o] - vp;
+      if (RESID) vp = bq[3] - vp;
       ys[3 * fs + o] = vp;
     }
     // advance the windows
