@@ -100,6 +100,8 @@ struct elh_handle {
   KrylovWS kout[2], kin[2];  // outer (level 0, f64; Z f64/f32), inner (coarsest; f64/f32)
   DevBuf part, dots, coef, tmpvec;
   DevBuf gstate, gpart, gdots, gnrm, gcoef, gscale, ones;  // device-resident GMRES
+  DevBuf dq64, dq32;                                        // dense coarsest inverse (Q = inv(H_s^T))
+  int64_t dn = 0;
   hipStream_t cap = nullptr;                               // stream used only to record graphs
   std::vector<GraphEntry> graphs;
   int use_graphs = 1;                                      // ELH_GRAPHS=0 disables capture
@@ -158,7 +160,6 @@ static int check_desc(const elh_desc* d) {
   if (d->nu1 < 0 || d->nu2 < 0) return fail(ELH_ERR_ARG, "nu1/nu2 must be >= 0");
   if (d->cycle_calls != 1 && d->cycle_calls != 2) return fail(ELH_ERR_ARG, "cycle_calls must be 1 (V) or 2 (W)");
   if (d->coarse_mode < 0 || d->coarse_mode > 2) return fail(ELH_ERR_ARG, "bad coarse_mode");
-  if (d->coarse_mode == ELH_COARSE_DENSE) return fail(ELH_ERR_ARG, "ELH_COARSE_DENSE is not available in this build");
   if (d->coarse_mode != ELH_COARSE_DENSE && d->coarse_sweeps < 1) return fail(ELH_ERR_ARG, "coarse_sweeps must be >= 1");
   if (d->coarse_mode == ELH_COARSE_KRYLOV && (d->coarse_restart < 1 || d->coarse_maxit < 1))
     return fail(ELH_ERR_ARG, "coarse_restart/coarse_maxit must be >= 1");
@@ -189,6 +190,12 @@ static int build_hierarchy(elh_handle* H, const double* lam, const double* mu, c
   HIPCHK(hipStreamSynchronize(st));
   return 0;
 }
+
+// Dense coarsest-level inverse (ELH_COARSE_DENSE): columns of H_s from
+// applying it to unit vectors (boundary-face unknowns made identity), then
+// Gauss-Jordan inversion of H_s^T on the device.
+static constexpr int64_t DENSE_MAX = 8192;
+static int build_dense(elh_handle* H);
 
 extern "C" int elh_create(const elh_desc* desc, const double* lam, const double* mu, const double* rho,
                           void* stream, elh_handle** out) {
@@ -259,6 +266,7 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
     return fail(ELH_ERR_OOM, "pinned host allocation failed");
   }
   rc = build_hierarchy(H, lam, mu, rho);
+  if (!rc && desc->coarse_mode == ELH_COARSE_DENSE) rc = build_dense(H);
   if (rc) {
     elh_destroy(H);
     return rc;
@@ -271,7 +279,9 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
 extern "C" int elh_set_media(elh_handle* H, const double* lam, const double* mu, const double* rho) {
   if (!H || !H->ok) return fail(ELH_ERR_STATE, "invalid handle");
   if (!lam || !mu || !rho) return fail(ELH_ERR_ARG, "media pointers must be non-NULL");
-  return build_hierarchy(H, lam, mu, rho);
+  int rc = build_hierarchy(H, lam, mu, rho);
+  if (!rc && H->d.coarse_mode == ELH_COARSE_DENSE) rc = build_dense(H);
+  return rc;
 }
 
 extern "C" int elh_destroy(elh_handle* H) {
@@ -290,7 +300,7 @@ extern "C" int elh_destroy(elh_handle* H) {
   }
   release(H->part); release(H->dots); release(H->coef); release(H->tmpvec);
   release(H->gstate); release(H->gpart); release(H->gdots); release(H->gnrm); release(H->gcoef);
-  release(H->gscale); release(H->ones);
+  release(H->gscale); release(H->ones); release(H->dq64); release(H->dq32);
   for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
   H->graphs.clear();
   if (H->cap) (void)hipStreamDestroy(H->cap);
@@ -578,6 +588,41 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
   return 0;
 }
 
+static int build_dense(elh_handle* H) {
+  const int l = H->nlev - 1;
+  LevelData& L = H->lv[l];
+  const int64_t N = L.vs;
+  if (N > DENSE_MAX) return fail(ELH_ERR_ARG, "dense coarsest solve needs <= %lld unknowns, level %d has %lld",
+                                 (long long)DENSE_MAX, l, (long long)N);
+  DevBuf E, A, col, piv, isb;
+  int rc = 0;
+  const size_t mat = (size_t)N * N * 16;
+  if (ensure(E, mat) || ensure(A, mat) || ensure(col, (N + 1) * 16) || ensure(piv, 64) || ensure(isb, N * 4) ||
+      ensure(H->dq64, mat) || ensure(H->dq32, mat / 2)) {
+    release(E); release(A); release(col); release(piv); release(isb);
+    return ELH_ERR_OOM;
+  }
+  std::vector<int> hb(N, 0);
+  for (int f = 0; f < H->d.dim; ++f)
+    for (int64_t c = 0; c < L.fs; ++c) {
+      int idx[3] = {(int)(c % L.n[0]), (int)((c / L.n[0]) % L.n[1]), (int)(c / ((int64_t)L.n[0] * L.n[1]))};
+      if (idx[f] == 0) hb[f * L.fs + c] = 1;
+    }
+  hipStream_t st = H->st;
+  if (hipMemcpy(isb.p, hb.data(), N * 4, hipMemcpyHostToDevice) != hipSuccess) rc = fail(ELH_ERR_HIP, "upload failed");
+  if (!rc) rc = launch_dense_assemble_prep(N, E.p, st);
+  // A[j] = H_s e_j  (row-major A = H_s^T); batched apply over the N unit vectors
+  if (!rc) rc = launch_apply<double>(largs<double>(H, l, true), H->d.dim, false, E.p, nullptr, A.p, (int)N, st);
+  if (!rc) rc = launch_dense_fix(N, (const int*)isb.p, A.p, st);
+  if (!rc) rc = launch_dense_invert(N, A.p, H->dq64.p, col.p, (int*)piv.p, st);
+  if (!rc) rc = launch_scale_copy<cx<double>, cx<float>>(nullptr, H->dq64.p, 0, H->dq32.p, 0, N * N, 1, st);
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(ELH_ERR_HIP, "dense coarse setup failed");
+  if (rc > 0) rc = fail(ELH_ERR_HIP, "dense coarse setup launch failed");
+  release(E); release(A); release(col); release(piv); release(isb);
+  H->dn = N;
+  return rc;
+}
+
 // Fixed-budget restarted GMRES with all bookkeeping on the device (no host
 // synchronisation, graph-capturable).  Same algorithm as gmres() with
 // rtol = 0: classical Gram-Schmidt, complex Givens, restart every m steps,
@@ -635,6 +680,11 @@ static int coarse_solve(elh_handle* H, bool adj, const void* b, void* x, int nrh
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const elh_desc& d = H->d;
   if (d.coarse_mode == ELH_COARSE_RELAX) return op_sweeps_from_zero<T>(H, l, adj, b, x, nrhs, d.coarse_sweeps);
+  if (d.coarse_mode == ELH_COARSE_DENSE) {
+    // Q = inv(H_s^T):  H_s^{-1} b = Q^T b,  (H_s^H)^{-1} b = conj(Q) b
+    const void* Q = prec == 0 ? H->dq64.p : H->dq32.p;
+    return launch_dense_mv<T>(H->dn, Q, adj ? 0 : 1, adj ? 1 : 0, b, x, nrhs, H->st);
+  }
   if (nrhs > MAXRHS_KRYLOV) return fail(ELH_ERR_ARG, "at most %d right-hand sides with the Krylov coarse solve", MAXRHS_KRYLOV);
   // ELH_COARSE_KRYLOV: GMRES on H_s preconditioned by Vanka sweeps
   LevelData& L = H->lv[l];

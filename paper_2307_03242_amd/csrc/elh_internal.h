@@ -40,6 +40,12 @@ template <typename TX, typename TY>
 int launch_scale_copy(const double* a, const void* x, int64_t xstride, void* y, int64_t ystride, int64_t len,
                       int nrhs, hipStream_t st);
 int launch_zero(void* p, int64_t bytes, hipStream_t st);
+int launch_dense_assemble_prep(int64_t N, void* E, hipStream_t st);
+int launch_dense_fix(int64_t N, const int* isb, void* A, hipStream_t st);
+int launch_dense_invert(int64_t N, void* A, void* B, void* col, int* piv, hipStream_t st);
+template <typename T>
+int launch_dense_mv(int64_t N, const void* Q, int transposed, int cj, const void* b, void* x, int nrhs,
+                    hipStream_t st);
 int launch_gradient(const LevelArgs<double>& L, int dim, int nrhs, const void* u, const void* v, double* gl,
                     double* gm, double* gr, hipStream_t st);
 int launch_gm_start(int nrhs, const double* nrm2, double* st, double* scale, hipStream_t s);

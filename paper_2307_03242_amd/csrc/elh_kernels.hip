@@ -771,6 +771,171 @@ int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStre
   return (int)hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Dense coarsest-level solve (the paper's LU choice for 2D): the shifted
+// operator is assembled by applying it to unit vectors, inverted once by
+// Gauss-Jordan elimination with partial pivoting, and applied as a dense
+// matrix-vector product.  A is row-major N x N (A = H^T after assembly).
+// ---------------------------------------------------------------------------
+__global__ void k_unit_vectors(int64_t N, cx<double>* __restrict__ E) {
+  // E: N vectors of length N, E[j][i] = (i == j)
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * N) return;
+  int64_t j = t / N, i = t % N;
+  E[t] = mk(i == j ? 1.0 : 0.0, 0.0);
+}
+
+// rows of A (= columns of H) that are boundary faces: identity
+__global__ void k_fix_boundary_rows(int64_t N, const int* __restrict__ isb, cx<double>* __restrict__ A) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  if (isb[i]) A[i * N + i] = mk(1.0, 0.0);
+}
+
+__global__ void k_gj_pivot(int64_t N, int64_t k, const cx<double>* __restrict__ A, int* __restrict__ piv,
+                           cx<double>* __restrict__ pval) {
+  __shared__ double best[256];
+  __shared__ int64_t arg[256];
+  double b = -1.0;
+  int64_t a = k;
+  for (int64_t i = k + threadIdx.x; i < N; i += blockDim.x) {
+    double v = abs2(A[i * N + k]);
+    if (v > b) { b = v; a = i; }
+  }
+  best[threadIdx.x] = b;
+  arg[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      double ob = best[threadIdx.x + o];
+      int64_t oa = arg[threadIdx.x + o];
+      if (ob > best[threadIdx.x] || (ob == best[threadIdx.x] && oa < arg[threadIdx.x])) {
+        best[threadIdx.x] = ob;
+        arg[threadIdx.x] = oa;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    piv[0] = (int)arg[0];
+    pval[0] = A[arg[0] * N + k];  // read before any block of the swap kernel writes
+  }
+}
+
+// swap rows k and piv of [A | B], scale row k by 1/pivot, save column k
+__global__ void k_gj_swap_scale(int64_t N, int64_t k, const int* __restrict__ piv, cx<double>* __restrict__ A,
+                                cx<double>* __restrict__ B, const cx<double>* __restrict__ pval) {
+  const int64_t p = piv[0];
+  const cx<double> pv = pval[0];
+  const double ip = 1.0 / abs2(pv);
+  const cx<double> r = mk(pv.re * ip, -pv.im * ip);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < 2 * N; j += (int64_t)gridDim.x * blockDim.x) {
+    cx<double>* M = j < N ? A : B;
+    const int64_t jj = j < N ? j : j - N;
+    cx<double> vk = M[k * N + jj], vp = M[p * N + jj];
+    if (p != k) M[p * N + jj] = vk;
+    M[k * N + jj] = vp * r;
+  }
+}
+
+__global__ void k_gj_column(int64_t N, int64_t k, const cx<double>* __restrict__ A, cx<double>* __restrict__ col) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) col[i] = (i == k) ? czero<double>() : A[i * N + k];
+}
+
+__global__ void k_gj_eliminate(int64_t N, int64_t k, const cx<double>* __restrict__ col, cx<double>* __restrict__ A,
+                               cx<double>* __restrict__ B) {
+  const int64_t i = blockIdx.y;
+  const cx<double> f = col[i];
+  if (f.re == 0.0 && f.im == 0.0) return;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < 2 * N; j += (int64_t)gridDim.x * blockDim.x) {
+    if (j < N) {
+      if (j >= k) A[i * N + j] -= f * A[k * N + j];
+    } else {
+      B[i * N + (j - N)] -= f * B[k * N + (j - N)];
+    }
+  }
+}
+
+int launch_dense_assemble_prep(int64_t N, void* E, hipStream_t st) {
+  hipLaunchKernelGGL(k_unit_vectors, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, N, (cx<double>*)E);
+  return (int)hipGetLastError();
+}
+int launch_dense_fix(int64_t N, const int* isb, void* A, hipStream_t st) {
+  hipLaunchKernelGGL(k_fix_boundary_rows, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, isb,
+                     (cx<double>*)A);
+  return (int)hipGetLastError();
+}
+// Gauss-Jordan inverse: A is destroyed, B (identity on entry) becomes A^{-1}
+int launch_dense_invert(int64_t N, void* A, void* B, void* col, int* piv, hipStream_t st) {
+  cx<double>* a = (cx<double>*)A;
+  cx<double>* b = (cx<double>*)B;
+  cx<double>* c = (cx<double>*)col;
+  hipLaunchKernelGGL(k_unit_vectors, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, N, b);
+  for (int64_t k = 0; k < N; ++k) {
+    // col has N+1 entries: col[N] carries the pivot value
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, st, N, k, (const cx<double>*)a, piv, c + N);
+    hipLaunchKernelGGL(k_gj_swap_scale, dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, st, N, k,
+                       (const int*)piv, a, b, (const cx<double>*)(c + N));
+    hipLaunchKernelGGL(k_gj_column, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, k,
+                       (const cx<double>*)a, c);
+    unsigned gx = (unsigned)((2 * N + 255) / 256);
+    if (gx > 16) gx = 16;
+    hipLaunchKernelGGL(k_gj_eliminate, dim3(gx, (unsigned)N), dim3(256), 0, st, N, k, (const cx<double>*)c, a, b);
+  }
+  return (int)hipGetLastError();
+}
+
+// x[s] = op(Q) b[s] with Q row-major N x N.  transposed: x_i = sum_j Q[j][i] b_j
+// (coalesced over i); otherwise x_i = sum_j conj?(Q[i][j]) b_j.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_mv(int64_t N, const cx<T>* __restrict__ Q, int transposed, int cj,
+                                                   const cx<T>* __restrict__ b, cx<T>* __restrict__ x, int nrhs) {
+  const int s = blockIdx.y;
+  const cx<T>* bs = b + (int64_t)s * N;
+  if (transposed) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    cx<T> acc = czero<T>();
+    for (int64_t j = 0; j < N; ++j) {
+      cx<T> q = Q[j * N + i];
+      if (cj) q = conj(q);
+      acc += q * bs[j];
+    }
+    x[(int64_t)s * N + i] = acc;
+  } else {
+    // one wavefront per row
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (row >= N) return;
+    cx<T> acc = czero<T>();
+    for (int64_t j = lane; j < N; j += 64) {
+      cx<T> q = Q[row * N + j];
+      if (cj) q = conj(q);
+      acc += q * bs[j];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      acc.re += __shfl_down(acc.re, o);
+      acc.im += __shfl_down(acc.im, o);
+    }
+    if (lane == 0) x[(int64_t)s * N + row] = acc;
+  }
+}
+
+template <typename T>
+int launch_dense_mv(int64_t N, const void* Q, int transposed, int cj, const void* b, void* x, int nrhs,
+                    hipStream_t st) {
+  if (transposed)
+    hipLaunchKernelGGL((k_dense_mv<T>), dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, N,
+                       (const cx<T>*)Q, 1, cj, (const cx<T>*)b, (cx<T>*)x, nrhs);
+  else
+    hipLaunchKernelGGL((k_dense_mv<T>), dim3((unsigned)((N + 3) / 4), nrhs), dim3(256), 0, st, N, (const cx<T>*)Q,
+                       0, cj, (const cx<T>*)b, (cx<T>*)x, nrhs);
+  return (int)hipGetLastError();
+}
+template int launch_dense_mv<double>(int64_t, const void*, int, int, const void*, void*, int, hipStream_t);
+template int launch_dense_mv<float>(int64_t, const void*, int, int, const void*, void*, int, hipStream_t);
+
 __global__ void k_fill_zero(uint2* p, int64_t n8) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n8; i += (int64_t)gridDim.x * blockDim.x) p[i] = make_uint2(0, 0);
