@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=64, help="oracle sample grid (cells per axis)")
     ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-sources, uneven-batch and gradient measurements")
     return ap.parse_args()
 
 
@@ -89,6 +91,123 @@ def cpu_baseline(args, gpu_iters, cfg):
             "sample": "%d outer FGMRES(5)+V-cycle iterations of the float64 oracle on a %d^3 grid "
                       "(same media recipe, %.1f s), scaled per cell to %d^3 and to the GPU's %d iterations"
                       % (info["iters"], n, dt, args.n, gpu_iters)}
+
+
+def solver_cfg(args, omega, levels=None):
+    damping = [float(v) for v in args.damping.split(",")]
+    return dict(h=1.0, omega=omega, gamma=0.01, alpha=args.alpha, beta=2 / 3, abl_width=args.abl * 1.0,
+                abl_amp=2.0, levels=levels or args.levels, nu1=1, nu2=1, cycle=args.cycle, damping=damping,
+                coarse_mode=args.coarse, coarse_sweeps=args.coarse_sweeps, coarse_restart=5,
+                coarse_maxit=args.coarse_maxit, coarse_rtol=args.coarse_rtol)
+
+
+def extras(args):
+    """Secondary measurements of the other production forms (one run each,
+    setup excluded): batched sources, uneven-grid batch, FWI gradient."""
+    import os
+    import torch
+    from paper_2307_03242_amd import Problem
+    from paper_2307_03242_amd.autograd import misfit
+    from synthetic import make_media, point_source, omega_for_ppw, lattice_sources
+    out = {}
+
+    def media(shape, seed):
+        m = make_media(shape, seed)
+        return m, [torch.from_numpy(m[k]).cuda() for k in ("lam", "mu", "rho")]
+
+    # 32 point sources on a 160^3 grid: one batched float32-cycle solve vs the
+    # plain float64 solver (float64 cycle, no graphs) one source at a time
+    n = 160
+    shape = (n, n, n)
+    m, med = media(shape, 4)
+    om = omega_for_ppw(m["vs"].min(), 1.0, 10)
+    q = torch.from_numpy(lattice_sources(shape, 4, 8, depth_index=args.abl + 2, margin=args.abl)).cuda()
+    p32 = Problem(*med, precond_dtype=torch.complex64, **solver_cfg(args, om))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info, code = p32.solve(q, rtol=args.rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    del p32
+    torch.cuda.empty_cache()
+    old = os.environ.get("ELH_GRAPHS")
+    os.environ["ELH_GRAPHS"] = "0"
+    try:
+        p64 = Problem(*med, precond_dtype=torch.complex128, **solver_cfg(args, om))
+    finally:
+        if old is None:
+            del os.environ["ELH_GRAPHS"]
+        else:
+            os.environ["ELH_GRAPHS"] = old
+    nsingle = 4
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(nsingle):
+        p64.solve(q[s:s + 1].contiguous(), rtol=args.rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / nsingle
+    del p64
+    torch.cuda.empty_cache()
+    out["batched_sources"] = {
+        "workload": "160^3, seed 4, 32 point sources (u_3, 4x8 lattice), float32 cycle, one batched solve",
+        "solves_per_s": 32 / tb, "iters_max": max(i["iters"] for i in info), "code": code,
+        "baseline_fp64_single_solves_per_s": 1.0 / ts,
+        "baseline": "float64 cycle, no graphs, one source per solve (%d of the 32 sources timed)" % nsingle,
+        "speedup": ts * 32 / tb}
+
+    # 12 independent problems of uneven size, solved together (one stream each)
+    sizes = [64, 80, 96, 112, 128, 144, 160, 176, 192, 96, 128, 160]
+    probs, qs = [], []
+    for i, nn in enumerate(sizes):
+        sh = (nn, nn, nn)
+        mm, md = media(sh, 100 + i)
+        omi = omega_for_ppw(mm["vs"].min(), 1.0, 10)
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            probs.append(Problem(*md, precond_dtype=torch.complex64, **solver_cfg(args, omi)))
+        qs.append(torch.from_numpy(point_source(sh)[None]).cuda())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos, code = Problem.solve_batch(probs, qs, rtol=args.rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    tc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for p, qq in zip(probs, qs):
+        p.solve(qq, rtol=args.rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    tq = time.perf_counter() - t0
+    out["uneven_batch"] = {
+        "workload": "12 problems, n = %s (seeds 100-111), 1 centred source each, float32 cycle" % sizes,
+        "solves_per_s_concurrent": len(sizes) / tc, "solves_per_s_sequential": len(sizes) / tq,
+        "iters": [i[0]["iters"] for i in infos], "code": code}
+    del probs, qs
+    torch.cuda.empty_cache()
+
+    # FWI gradient on 128^3: 8 sources, receivers on the plane at depth 18
+    n = 128
+    shape = (n, n, n)
+    mt, medt = media(shape, 500)
+    om = omega_for_ppw(mt["vs"].min(), 1.0, 10)
+    src = torch.from_numpy(lattice_sources(shape, 2, 4, depth_index=18, margin=args.abl)).cuda()
+    mask = torch.zeros((4,) + shape, dtype=torch.bool, device="cuda")
+    mask[:3, 18, args.abl:-args.abl, args.abl:-args.abl] = True
+    pt = Problem(*medt, precond_dtype=torch.complex64, **solver_cfg(args, om))
+    d_obs, _, _ = pt.solve(src, rtol=args.rtol, maxit=args.maxit)
+    d_obs = d_obs * mask
+    z, y, x = torch.meshgrid(*[torch.arange(n, dtype=torch.float64, device="cuda") + 0.5] * 3, indexing="ij")
+    blob = 1.0 - 0.08 * torch.exp(-((z - n / 2) ** 2 + (y - n / 2) ** 2 + (x - n / 2) ** 2) / (2 * 12.0 ** 2))
+    params = [(mm * blob).clone().requires_grad_(True) for mm in medt]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi = misfit(pt, *params, src, mask, d_obs, rtol=args.rtol, maxit=args.maxit)
+    phi.backward()
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    out["fwi_gradient"] = {
+        "workload": "128^3, true medium seed 500, start = true with an 8%% central Gaussian anomaly, 8 sources, "
+                    "receivers on the plane at depth 18; forward + adjoint solves to %.0e + gradient kernel" % args.rtol,
+        "seconds": tg, "misfit": float(phi.item())}
+    return out
 
 
 def main():
@@ -197,6 +316,11 @@ def main():
     }
     del p32
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        try:
+            out["production_forms"] = extras(args)
+        except Exception as e:  # report, never hide
+            out["production_forms"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(args, it32, cfg)

@@ -181,6 +181,17 @@ int elh_solve(elh_handle* h, int nrhs, const void* q, void* u,
 int elh_solve_adjoint(elh_handle* h, int nrhs, const void* r, void* v,
                       const elh_solve_opts* opts, elh_solve_stats* stats);
 
+/* Solve several independent problems together: problem i (handle h[i],
+ * any grid size) solves nrhs[i] right-hand sides q[i] -> u[i] exactly as
+ * elh_solve would.  Each problem is driven by its own host thread, so the
+ * kernels of different problems overlap on the GPU when the handles were
+ * created on different streams (the batched-sources / uneven-grids form of
+ * the solver).  stats: (host) sum(nrhs) records in problem order, may be
+ * NULL.  Returns the most severe status of all problems. */
+int elh_solve_batch(int nprob, elh_handle* const* h, const int* nrhs,
+                    const void* const* q, void* const* u,
+                    const elh_solve_opts* opts, elh_solve_stats* stats);
+
 /* Parameter gradient of an FWI misfit by the adjoint state:
  *   g_m(c) = - Re sum_s v_s^H (dH/dm_c) u_s,  m in {lam, mu, rho},
  * for forward fields u and adjoint fields v (float64, nrhs each, level 0).

@@ -14,7 +14,7 @@ ELH_COARSE_KRYLOV, ELH_COARSE_DENSE, ELH_COARSE_RELAX = 0, 1, 2
 EXPORTED = [
     "elh_create", "elh_set_media", "elh_destroy", "elh_apply", "elh_residual",
     "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_coarse_solve",
-    "elh_vcycle", "elh_solve", "elh_solve_adjoint", "elh_gradient",
+    "elh_vcycle", "elh_solve", "elh_solve_adjoint", "elh_solve_batch", "elh_gradient",
     "elh_level_info", "elh_status_string", "elh_last_error",
 ]
 
@@ -71,6 +71,9 @@ def load():
         "elh_vcycle": [H, ip, ip, ip, vp, vp],
         "elh_solve": [H, ip, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
         "elh_solve_adjoint": [H, ip, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
+        "elh_solve_batch": [ip, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                            ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
         "elh_gradient": [H, ip, vp, vp, vp, vp, vp],
         "elh_level_info": [H, ip, ctypes.POINTER(ctypes.c_int), dp],
         "elh_status_string": [ip],

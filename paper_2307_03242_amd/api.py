@@ -188,6 +188,35 @@ class Problem:
     def solve_adjoint(self, r, restart=5, maxit=500, rtol=1e-6, out=None):
         return self._solve(self.lib.elh_solve_adjoint, r, restart, maxit, rtol, out)
 
+    @staticmethod
+    def solve_batch(problems, qs, restart=5, maxit=500, rtol=1e-6):
+        """Solve independent problems together (one host thread each; create
+        the problems on different streams so their kernels overlap).
+        Returns (list of u, list of info lists, code)."""
+        if len(problems) != len(qs) or not problems:
+            raise ValueError("one right-hand-side batch per problem")
+        lib = problems[0].lib
+        n = len(problems)
+        us, nr = [], []
+        for p, q in zip(problems, qs):
+            if q.dtype != torch.complex128:
+                raise TypeError("right-hand sides must be complex128")
+            nr.append(p._vec(q, 0))
+            us.append(torch.empty_like(q))
+        hs = (ctypes.c_void_p * n)(*[p.handle.value for p in problems])
+        nrh = (ctypes.c_int * n)(*nr)
+        qp = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+        up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        opts = L.SolveOpts(restart, maxit, rtol)
+        stats = (L.SolveStats * sum(nr))()
+        code = L.check(lib.elh_solve_batch(n, hs, nrh, qp, up, ctypes.byref(opts), stats))
+        infos, k = [], 0
+        for r in nr:
+            infos.append([dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres)
+                          for s in stats[k:k + r]])
+            k += r
+        return us, infos, code
+
     def gradient(self, u, v):
         nrhs = self._vec(u, 0)
         g = [torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(3)]

@@ -7,7 +7,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <string>
+
+#include <atomic>
 #include <complex>
+#include <thread>
 #include <vector>
 
 #include "../../include/elh.h"
@@ -49,7 +53,7 @@ struct DevBuf {
 };
 
 // bumped on every (re)allocation: captured graphs embed buffer addresses
-static uint64_t g_alloc_gen = 1;
+static std::atomic<uint64_t> g_alloc_gen{1};
 
 static int ensure(DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes) return 0;
@@ -958,6 +962,38 @@ extern "C" int elh_solve(elh_handle* H, int nrhs, const void* q, void* u, const 
 extern "C" int elh_solve_adjoint(elh_handle* H, int nrhs, const void* r, void* v, const elh_solve_opts* opts,
                                  elh_solve_stats* stats) {
   return solve_impl(H, true, nrhs, r, v, opts, stats);
+}
+
+extern "C" int elh_solve_batch(int nprob, elh_handle* const* hs, const int* nrhs, const void* const* q,
+                               void* const* u, const elh_solve_opts* opts, elh_solve_stats* stats) {
+  if (nprob < 1 || !hs || !nrhs || !q || !u || !opts) return fail(ELH_ERR_ARG, "invalid batch arguments");
+  std::vector<int> off(nprob + 1, 0);
+  for (int i = 0; i < nprob; ++i) {
+    if (!hs[i] || !hs[i]->ok) return fail(ELH_ERR_STATE, "invalid handle %d", i);
+    if (nrhs[i] < 1) return fail(ELH_ERR_ARG, "nrhs[%d] must be >= 1", i);
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(ELH_ERR_ARG, "handle %d appears twice", i);
+    off[i + 1] = off[i] + nrhs[i];
+  }
+  std::vector<int> rcs(nprob, 0);
+  std::vector<std::string> errs(nprob);
+  std::vector<std::thread> th;
+  for (int i = 0; i < nprob; ++i)
+    th.emplace_back([&, i]() {
+      rcs[i] = solve_impl(hs[i], false, nrhs[i], q[i], u[i], opts, stats ? stats + off[i] : nullptr);
+      if (rcs[i] < 0) errs[i] = g_err;  // thread-local message of the worker
+    });
+  for (auto& t : th) t.join();
+  int worst = ELH_OK;
+  for (int i = 0; i < nprob; ++i) {
+    if (rcs[i] < 0 && (worst >= 0 || rcs[i] < worst)) {
+      worst = rcs[i];
+      snprintf(g_err, sizeof(g_err), "problem %d: %s", i, errs[i].c_str());
+    } else if (rcs[i] > 0 && worst == ELH_OK) {
+      worst = rcs[i];
+    }
+  }
+  return worst;
 }
 
 extern "C" int elh_gradient(elh_handle* H, int nrhs, const void* u, const void* v, double* g_lam, double* g_mu,

@@ -374,3 +374,26 @@ def test_config_2d_64_dense_fp64():
     _, oinfo = C.solve(lv, q[0], C.CycleParams(levels=2, alpha=0.1, damping=(0.55,), coarse="direct"),
                        tol=1e-8, maxit=500)
     assert abs(oinfo["iters"] - info[0]["iters"]) <= 2
+
+
+def test_solve_batch_uneven_grids_equal_single_solves():
+    """independent problems of different grid sizes, each on its own stream,
+    solved together equal their individual solves exactly"""
+    from paper_2307_03242_amd import Problem
+    shapes = [(16, 16, 16), (24, 24, 24), (16, 24, 32)]
+    probs, qs = [], []
+    streams = [torch.cuda.Stream() for _ in shapes]
+    for i, (shape, st) in enumerate(zip(shapes, streams)):
+        P = _params(shape, levels=3, coarse="krylov", seed=100 + i)
+        with torch.cuda.stream(st):
+            probs.append(_gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=4, precond=torch.complex64,
+                                      cycle="W"))
+        qs.append(_dev(np.stack([point_source(shape)] * (1 + i % 2))))
+    torch.cuda.synchronize()
+    us, infos, code = Problem.solve_batch(probs, qs, rtol=1e-8, maxit=300)
+    assert code == 0
+    for p, q, u, info in zip(probs, qs, us, infos):
+        u1, info1, _ = p.solve(q, rtol=1e-8, maxit=300)
+        torch.cuda.synchronize()
+        assert np.array_equal(_host(u), _host(u1))
+        assert [i["iters"] for i in info] == [i["iters"] for i in info1]
