@@ -111,8 +111,9 @@ struct elh_handle {
   int use_graphs = 1;                                      // ELH_GRAPHS=0 disables capture
   double* hdots = nullptr;  // pinned host mirror
   double* hcoef = nullptr;
-  int generic_stencil = 0;  // ELH_STENCIL=generic selects the reference-structured kernel
+  int stencil = 0;          // ELH_STENCIL: 0 wavefront march (default), 1 LDS-tiled, 2 point-wise
   int zchunk = 32;          // x_3 planes per workgroup of the tiled stencil (ELH_ZCHUNK)
+  int tile_y = 10;          // tile height (slots) of the float32 tiled stencil (ELH_TILE_Y: 6 or 10)
   int ok = 0;
 };
 
@@ -212,9 +213,12 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
   H->d = *desc;
   {
     const char* e = getenv("ELH_STENCIL");
-    H->generic_stencil = (e && strcmp(e, "generic") == 0) ? 1 : 0;
+    if (e && strcmp(e, "tiled") == 0) H->stencil = 1;
+    if (e && strcmp(e, "generic") == 0) H->stencil = 2;
     const char* z = getenv("ELH_ZCHUNK");
     if (z && atoi(z) > 0) H->zchunk = atoi(z);
+    const char* ty = getenv("ELH_TILE_Y");
+    if (ty && (atoi(ty) == 6 || atoi(ty) == 10)) H->tile_y = atoi(ty);
     const char* g = getenv("ELH_GRAPHS");
     if (g && strcmp(g, "0") == 0) H->use_graphs = 0;
   }
@@ -344,11 +348,14 @@ static int ensure_cycle_bufs(elh_handle* H, int prec, int nrhs) {
 // ---------------------------------------------------------------------------
 template <typename T>
 static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs) {
-  // the tiled kernel marches x_3 columns: it pays off once a level has
-  // enough columns to fill the chip; small coarse levels use one thread per cell
-  const int64_t small = 24 * 24 * 24;
-  if (H->d.dim == 3 && !adj && !H->generic_stencil && H->lv[l].fs >= small)
-    return launch_apply3d_tiled<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
+  // the marching kernels pay off once a level has enough x_3 columns to fill
+  // the chip; small coarse levels use one thread per cell
+  // (the wavefront march addresses a field with 32-bit byte offsets)
+  const bool fits32 = H->lv[l].fs * (int64_t)sizeof(cx<T>) <= (int64_t)0x7fffffff;
+  if (H->d.dim == 3 && !adj && H->stencil == 0 && fits32 && H->lv[l].fs >= 16 * 16 * 16)
+    return launch_apply3d_w3<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
+  if (H->d.dim == 3 && !adj && H->stencil == 1 && H->lv[l].fs >= 24 * 24 * 24)
+    return launch_apply3d_tiled<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->tile_y, H->st);
   return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);
 }
 

@@ -24,8 +24,14 @@ int launch_restrict(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const
 template <typename T>
 int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* e, void* x, int nrhs,
                        hipStream_t st);
+// 3D forward apply / residual, component-split wavefront march: three
+// wavefronts per x_2 row (one per displacement component) marching along
+// x_3, DPP for x_1 neighbours, one LDS hand-off per plane for the p row.
 template <typename T>
-int launch_apply3d_tiled(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
+int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
+                      hipStream_t st);
+template <typename T>
+int launch_apply3d_tiled(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc, int ty,
                          hipStream_t st);
 int launch_coarsen_media(int dim, const int* nf, const double* a, double* out, hipStream_t st);
 int launch_media_finish(int64_t n, const double* lam, const double* mu, const double* rho, double* kap, float* mu32,

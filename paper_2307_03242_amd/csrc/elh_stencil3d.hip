@@ -26,11 +26,9 @@
 namespace elh {
 
 constexpr int ST_TX = 64;             // slots along x_1 (one wavefront)
-constexpr int ST_TY = 6;              // slots along x_2
 constexpr int ST_OX = ST_TX - 2;      // outputs along x_1
-constexpr int ST_OY = ST_TY - 2;      // outputs along x_2
 
-template <typename T> struct Tile3 {
+template <typename T, int ST_TY> struct Tile3 {
   cx<T> R[3][ST_TY][ST_TX];    // raw u_k(t+1)
   cx<T> Z[3][ST_TY][ST_TX];    // A_3 u_k(t)
   cx<T> B1[3][ST_TY][ST_TX];   // A_1 u_k(t+1)
@@ -70,11 +68,12 @@ __device__ __forceinline__ T absorb_axis(T xp, T len, T w, T iw, T amp) {
   return amp * r * r;
 }
 
-template <typename T, bool RESID>
+template <typename T, bool RESID, int ST_TY>
 __global__ void __launch_bounds__(ST_TX * ST_TY)
 k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
                 int tiles_x, int tiles_y, int nzc, int zc, int ntiles, int per_xcd) {
-  __shared__ Tile3<T> S;
+  constexpr int ST_OY = ST_TY - 2;      // outputs along x_2
+  __shared__ Tile3<T, ST_TY> S;
   // XCD-aware tile number: workgroups are dealt round-robin to the 8 XCDs
   const int bid = blockIdx.x;
   const int tile = (bid & 7) * per_xcd + (bid >> 3);
@@ -91,7 +90,8 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
   const int z0 = tz * zc;
   const int z1 = min(z0 + zc, n3);
   const bool inplane = c1 >= 0 && c1 < n1 && c2 >= 0 && c2 < n2;
-  const bool outslot = lane >= 1 && lane <= ST_OX && row >= 1 && row <= ST_OY && inplane;
+  const bool inner_row = row >= 1 && row <= ST_OY;   // whole wavefronts: uniform branches
+  const bool outslot = lane >= 1 && lane <= ST_OX && inner_row && inplane;
   const int cc1 = min(max(c1, 0), n1 - 1), cc2 = min(max(c2, 0), n2 - 1);  // clamped (media)
   const int64_t fs = L.fs;
   const int64_t plane = (int64_t)n1 * n2;
@@ -234,7 +234,8 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
     for (int k = 0; k < 3; ++k) {
       const cx<T> Zk = S.Z[k][row][lane];
       S.B1[k][row][lane] = q * (S.R[k][row][lm] + S.R[k][row][lp]) + T(0.5) * U[k][2];
-      S.Y1[k][row][lane] = beta * U[k][1] + omb * (q * (S.Z[k][rm][lane] + S.Z[k][rp][lane]) + T(0.5) * Zk);
+      if (inner_row)  // Y_k1 is only read along x_1, by the output rows
+        S.Y1[k][row][lane] = beta * U[k][1] + omb * (q * (S.Z[k][rm][lane] + S.Z[k][rp][lane]) + T(0.5) * Zk);
       S.Y2[k][row][lane] = beta * U[k][1] + omb * (q * (S.Z[k][row][lm] + S.Z[k][row][lp]) + T(0.5) * Zk);
     }
     lds_barrier();
@@ -243,8 +244,10 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
     cx<T> out[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const cx<T> b1 = S.B1[k][row][lane];
-      Y3[k][2] = beta * U[k][2] + omb * (q * (S.B1[k][rm][lane] + S.B1[k][rp][lane]) + T(0.5) * b1);
+      if (inner_row) {  // Y_k3 only feeds the own column's output
+        const cx<T> b1 = S.B1[k][row][lane];
+        Y3[k][2] = beta * U[k][2] + omb * (q * (S.B1[k][rm][lane] + S.B1[k][rp][lane]) + T(0.5) * b1);
+      }
       if (emit) {
         const cx<T> y1 = S.Y1[k][row][lane], y2 = S.Y2[k][row][lane];
         const cx<T> y1m = S.Y1[k][row][lm], y1p = S.Y1[k][row][lp];
@@ -320,11 +323,12 @@ k_apply3d_tiled(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __rest
   }
 }
 
-template <typename T>
-int launch_apply3d_tiled(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
-                         hipStream_t st) {
+template <typename T, int TY>
+static int launch_tiled_ty(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
+                           hipStream_t st) {
+  constexpr int OY = TY - 2;
   const int tiles_x = (L.n[0] + ST_OX - 1) / ST_OX;
-  const int tiles_y = (L.n[1] + ST_OY - 1) / ST_OY;
+  const int tiles_y = (L.n[1] + OY - 1) / OY;
   if (zc <= 0) zc = 32;
   // keep at least ~2048 workgroups in flight: shorter x_3 chunks on small grids
   {
@@ -338,18 +342,28 @@ int launch_apply3d_tiled(const LevelArgs<T>& L, const void* x, const void* b, vo
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
   const int ntiles = (int)ntiles64;
   const int per_xcd = (ntiles + 7) / 8;
-  dim3 blk(ST_TX, ST_TY), grd(8 * per_xcd);
+  dim3 blk(ST_TX, TY), grd(8 * per_xcd);
   if (b)
-    hipLaunchKernelGGL((k_apply3d_tiled<T, true>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b, (cx<T>*)y,
-                       tiles_x, tiles_y, nzc, zc, ntiles, per_xcd);
-  else
-    hipLaunchKernelGGL((k_apply3d_tiled<T, false>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)nullptr,
+    hipLaunchKernelGGL((k_apply3d_tiled<T, true, TY>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b,
                        (cx<T>*)y, tiles_x, tiles_y, nzc, zc, ntiles, per_xcd);
+  else
+    hipLaunchKernelGGL((k_apply3d_tiled<T, false, TY>), grd, blk, 0, st, L, (const cx<T>*)x,
+                       (const cx<T>*)nullptr, (cx<T>*)y, tiles_x, tiles_y, nzc, zc, ntiles, per_xcd);
   return (int)hipGetLastError();
 }
-template int launch_apply3d_tiled<double>(const LevelArgs<double>&, const void*, const void*, void*, int, int,
+
+// ty: tile height in slots (6 or 10; float64 always uses 6 for its LDS size)
+template <typename T>
+int launch_apply3d_tiled(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc, int ty,
+                         hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    if (ty == 10) return launch_tiled_ty<T, 10>(L, x, b, y, nrhs, zc, st);
+  }
+  return launch_tiled_ty<T, 6>(L, x, b, y, nrhs, zc, st);
+}
+template int launch_apply3d_tiled<double>(const LevelArgs<double>&, const void*, const void*, void*, int, int, int,
                                           hipStream_t);
-template int launch_apply3d_tiled<float>(const LevelArgs<float>&, const void*, const void*, void*, int, int,
+template int launch_apply3d_tiled<float>(const LevelArgs<float>&, const void*, const void*, void*, int, int, int,
                                          hipStream_t);
 
 }  // namespace elh

@@ -1,0 +1,406 @@
+// Barrier-light 3D apply / residual of H^beta (forward operator) for gfx950.
+//
+// Same arithmetic as the point-wise kernel (Section 3.1, eq.
+// mixed-discretized; Section 5.3, eqs. dxSkew3D, massHO3D), organised for
+// the CDNA4 execution model:
+//  * a workgroup of three wavefronts owns one x_2 row of a 64-wide x_1
+//    segment and marches along x_3; wavefront k computes the rows of
+//    u_{k+1} (the u-u block of H is diagonal in the component) and its
+//    term of the divergence in the p row; lanes 0 and 63 are halo lanes
+//    (62 outputs per wavefront);
+//  * neighbours along x_1 are other lanes of the same wavefront, read with
+//    DPP wavefront shifts;
+//  * neighbours along x_2 (rows c-1, c+1; rho also at c-2) are loaded
+//    directly; the workgroups of neighbouring rows run on the same XCD
+//    (XCD-aware tile order), so these loads hit L2;
+//  * along x_3 each wavefront keeps rolling register windows of its one
+//    component (u at rows c-1..c+1, planes t-1 and t; the spread field Y_3;
+//    the carried x_3 flux; the rho-weighted u of the spread mass; mu; p);
+//  * the three divergence terms meet in LDS once per plane (one barrier,
+//    double-buffered by plane parity) and wavefront 0 writes the p row.
+// With S_l = beta*I + (1-beta) prod_{a != l} A_a (A_a = (1/4)[1 2 1] along
+// x_a) the fields Y_l = S_l u are formed once per point; the flux through a
+// face is mu_e (Y(hi) - Y(lo)) / h and the row is the difference of the two
+// fluxes beside it, as in the point-wise kernel.
+#include "elh_device.h"
+#include "elh_internal.h"
+
+namespace elh {
+
+namespace {
+
+constexpr int WV_LANES = 64;
+constexpr int WV_OUT = WV_LANES - 2;   // outputs per wave along x_1
+
+// DPP wavefront shifts: FROM_LEFT gives lane i the value of lane i-1,
+// FROM_RIGHT the value of lane i+1 (zero where that lane does not exist).
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <typename T> __device__ __forceinline__ T fromL(T v) { return dpp<DPP_WAVE_SHR1>(v); }
+template <typename T> __device__ __forceinline__ T fromR(T v) { return dpp<DPP_WAVE_SHL1>(v); }
+template <typename T> __device__ __forceinline__ cx<T> fromL(cx<T> v) { return mk(fromL(v.re), fromL(v.im)); }
+template <typename T> __device__ __forceinline__ cx<T> fromR(cx<T> v) { return mk(fromR(v.re), fromR(v.im)); }
+
+// amp * (delta/width)^2, delta the distance into the absorbing layer at
+// physical coordinate xp along an axis of physical length len.
+template <typename T>
+__device__ __forceinline__ T absorb(T xp, T len, T w, T iw, T amp) {
+  T d = (w - xp > T(0) ? w - xp : T(0)) + (xp - (len - w) > T(0) ? xp - (len - w) : T(0));
+  T r = d * iw;
+  return amp * r * r;
+}
+
+// Buffer resources (raw, stride 0): the plane offset of the march goes into
+// the scalar offset, the lane offsets stay fixed.  Offsets at or beyond the
+// resource size read as zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                           (int)(bytes > 0x7fffffffll ? 0x7fffffffll : bytes), 0x00020000);
+}
+template <typename V> __device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ cx<float> bload<cx<float>>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ cx<double> bload<cx<double>>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(cx<float> v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                        voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(cx<double> v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
+                                         voff, soff, 0);
+}
+
+// Workgroup barrier for the LDS hand-off of the divergence terms: waits for
+// this wave's LDS operations only, so buffer loads stay in flight.
+__device__ __forceinline__ void lds_barrier_w3() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+}
+
+}  // namespace
+
+template <typename T> struct W3Ctx {
+  int n1, n2, n3, plane, c1, c2, z0, z1;
+  bool inx, outlane;
+  int roff[4];  // in-plane cell numbers of rows c-2 .. c+1 (clamped)
+  bool rok[4];
+  int offLc;    // cell left of (c1, c2) (clamped)
+  __amdgpu_buffer_rsrc_t RX[4], RY[4], RB[4], RMU, RRHO, RKAP;
+  T beta, omb, ih, ih2, cn, omega2;
+  bool has_abl;
+  T h, len3, abl_w, abl_iw, abl_amp;
+  T gf;         // gamma (+alpha) + x_1 and x_2 parts of the layer at this wave's faces
+};
+
+template <int K, typename T, bool RESID>
+__device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
+  constexpr int CB = (int)sizeof(cx<T>), RBY = (int)sizeof(T);
+  const T q = T(0.25), hf = T(0.5);
+  const T beta = C.beta, omb = C.omb;
+  const int lane = threadIdx.x;
+  const int n3 = C.n3;
+  int vu[3], vr[4];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) vu[r] = C.roff[r + 1] * CB;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) vr[r] = C.roff[r] * RBY;
+  const int vrL = C.offLc * RBY;
+  auto zcl = [&](int z) { return min(max(z, 0), n3 - 1) * C.plane; };
+  // mask of u_{K+1} at row r (0: c-1, 1: c, 2: c+1) of plane z
+  auto uok = [&](int r, int z) {
+    bool ok = C.inx && C.rok[r + 1] && z >= 0 && z < n3;
+    if (K == 0) ok = ok && C.c1 > 0;
+    if (K == 1) ok = ok && C.c2 - 1 + r > 0;
+    if (K == 2) ok = ok && z > 0;
+    return ok;
+  };
+
+  // loads in flight for the next plane
+  cx<T> nu[3];
+  cx<T> npm, npc;
+  T nmu[3], nrho[4], nrhoL;
+  auto load_next = [&](int z) {
+    const int so = zcl(z) * CB, sr = zcl(z) * RBY;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) nu[r] = bload<cx<T>>(C.RX[K], vu[r], so);
+    npc = bload<cx<T>>(C.RX[3], vu[1], so);
+    if (K == 1) npm = bload<cx<T>>(C.RX[3], vu[0], so);
+    if (K == 1) {
+      nmu[0] = bload<T>(C.RMU, vr[1], sr);
+      nmu[1] = bload<T>(C.RMU, vr[2], sr);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) nmu[r] = bload<T>(C.RMU, vr[r + 1], sr);
+    }
+    if (K == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nrho[r] = bload<T>(C.RRHO, vr[r], sr);
+    } else {
+#pragma unroll
+      for (int r = 1; r < 4; ++r) nrho[r] = bload<T>(C.RRHO, vr[r], sr);
+    }
+    if (K == 0) nrhoL = bload<T>(C.RRHO, vrL, sr);
+  };
+
+  // windows (plane t is the output plane); UA/UB and WA/WB are used
+  // ping-pong: the step for plane t overwrites the plane t-1 half
+  cx<T> UA[3], UB[3];   // u at rows c-1, c, c+1
+  cx<T> WA, WB;         // rho_f u at row c
+  cx<T> Y3b, F3, Wmp;   // Y_3 at (c, t); x_3 flux below plane t (times h^2); rho_f u at (c-1, t) + (c+1, t)
+  cx<T> PA, PB, Pbm;    // p at (c, t-1) / (c, t) ping-pong; p at (c-1, t)
+  T MA[3], MB[3];       // mu at rows c-1, c, c+1 (planes t-1 / t ping-pong)
+  T rhob[3];            // rho at rows c-1, c, c+1 (plane t)
+  const int t0 = C.z0 - 2;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) UA[r] = UB[r] = czero<T>();
+  WA = WB = Y3b = F3 = Wmp = czero<T>();
+  PA = PB = Pbm = czero<T>();
+  {
+    const int sr = zcl(t0) * RBY;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      MA[r] = MB[r] = bload<T>(C.RMU, vr[r + 1], sr);
+      rhob[r] = bload<T>(C.RRHO, vr[r + 1], sr);
+    }
+  }
+  load_next(t0 + 1);
+
+  auto step = [&](int t, cx<T>(&UO)[3], cx<T>(&UC)[3], cx<T>& WO, cx<T>& WC, T(&MO)[3], T(&MC)[3], cx<T>& PO,
+                  cx<T>& PC) {
+    const int tn = t + 1;
+    const bool zok = tn >= 0 && tn < n3;
+    const int sc = zcl(t) * CB;
+    cx<T> bq = czero<T>();
+    if (RESID) bq = bload<cx<T>>(C.RB[K], vu[1], sc);
+    // plane t+1: masked u, p and the media this component uses
+    cx<T> Un[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) Un[r] = uok(r, tn) ? nu[r] : czero<T>();
+    const cx<T> Pnc = (C.inx && zok) ? npc : czero<T>();
+    const cx<T> Pnm = (K == 1 && C.inx && C.rok[1] && zok) ? npm : czero<T>();
+    T mun[3], rhon[3], rf[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      mun[r] = nmu[r];
+      rhon[r] = nrho[r + 1];
+    }
+    // face means of rho for this component at rows c-1, c, c+1
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      if (K == 0) rf[r] = hf * ((r == 1 ? nrhoL : fromL(rhon[r])) + rhon[r]);
+      if (K == 1) rf[r] = hf * (nrho[r] + rhon[r]);
+      if (K == 2) rf[r] = hf * (rhob[r] + rhon[r]);
+    }
+    load_next(t + 2);
+    T a3 = T(0);
+    if (C.has_abl) {
+      const T xp = (K == 2 ? T(t) : T(t) + hf) * C.h;
+      a3 = absorb<T>(xp, C.len3, C.abl_w, C.abl_iw, C.abl_amp);
+    }
+    const cx<T> Wn = rf[1] * Un[1];
+    const cx<T> Wmpn = rf[0] * Un[0] + rf[2] * Un[2];
+    // Y_3(t+1) = beta u + (1-beta) A_1 A_2 u at row c
+    const cx<T> V = q * (Un[0] + Un[2]) + hf * Un[1];
+    const cx<T> Y3n = beta * Un[1] + omb * (q * (fromL(V) + fromR(V)) + hf * V);
+    // A_3 u(t) at rows c-1, c, c+1; Y_1(t) (row c) and Y_2(t) (three rows)
+    cx<T> Z[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) Z[r] = q * (UO[r] + Un[r]) + hf * UC[r];
+    const cx<T> y1 = beta * UC[1] + omb * (q * (Z[0] + Z[2]) + hf * Z[1]);
+    cx<T> y2[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) y2[r] = beta * UC[r] + omb * (q * (fromL(Z[r]) + fromR(Z[r])) + hf * Z[r]);
+    const cx<T> d1lo = y1 - fromL(y1);
+    const cx<T> d1hi = fromR(d1lo);
+    const cx<T> d2lo = y2[1] - y2[0], d2hi = y2[2] - y2[1];
+    cx<T> acc, F3n, dv;
+    if (K == 0) {
+      // x_1 flux with cell mu; x_2 / x_3 fluxes with mu averaged over the
+      // four cells around the edge (pairs along x_1 first)
+      T MXb[3], MXn1;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) MXb[r] = hf * (fromL(MC[r]) + MC[r]);
+      MXn1 = hf * (fromL(mun[1]) + mun[1]);
+      acc = fromL(MC[1]) * d1lo - MC[1] * d1hi;
+      acc += (hf * (MXb[0] + MXb[1])) * d2lo - (hf * (MXb[1] + MXb[2])) * d2hi;
+      F3n = (hf * (MXb[1] + MXn1)) * (Y3n - Y3b);
+      dv = d1hi;
+    } else if (K == 1) {
+      const T MYb = hf * (MC[0] + MC[1]), MYn = hf * (mun[0] + mun[1]);
+      acc = MC[0] * d2lo - MC[1] * d2hi;
+      acc += (hf * (fromL(MYb) + MYb)) * d1lo - (hf * (MYb + fromR(MYb))) * d1hi;
+      F3n = (hf * (MYb + MYn)) * (Y3n - Y3b);
+      dv = d2hi;
+    } else {
+      const T MZm = hf * (MO[0] + MC[0]), MZc = hf * (MO[1] + MC[1]), MZp = hf * (MO[2] + MC[2]);
+      acc = (hf * (fromL(MZc) + MZc)) * d1lo - (hf * (MZc + fromR(MZc))) * d1hi;
+      acc += (hf * (MZm + MZc)) * d2lo - (hf * (MZc + MZp)) * d2hi;
+      F3n = MC[1] * (Y3n - Y3b);
+      dv = Y3n - Y3b;
+    }
+    acc = C.ih2 * (acc + F3 - F3n);
+    // spread mass with the attenuation of the output face
+    const cx<T> nb = fromL(WC) + fromR(WC) + Wmp + WO + Wn;
+    const cx<T> sm = beta * WC + C.cn * nb;
+    acc -= mk(C.omega2, -C.omega2 * (C.gf + a3)) * sm;
+    // coupling with p: the cell above the face minus the cell below
+    if (K == 0) acc += C.ih * (PC - fromL(PC));
+    if (K == 1) acc += C.ih * (PC - Pbm);
+    if (K == 2) acc += C.ih * (PC - PO);
+    const bool emit = C.outlane && t >= C.z0;
+    if (emit) {
+      const bool face = K == 0 ? C.c1 > 0 : (K == 1 ? C.c2 > 0 : t > 0);
+      cx<T> v = face ? acc : czero<T>();
+      if (RESID && face) v = bq - v;
+      bstore(v, C.RY[K], vu[1], sc);
+    }
+    // divergence term of the p row of cell (c1, c2, t)
+    DV[t & 1][K][lane] = C.ih * dv;
+    // advance the windows: plane t+1 replaces plane t-1
+    F3 = F3n;
+    Y3b = Y3n;
+    WO = Wn;
+    Wmp = Wmpn;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      UO[r] = Un[r];
+      MO[r] = mun[r];
+      rhob[r] = rhon[r];
+    }
+    PO = Pnc;
+    Pbm = Pnm;
+    lds_barrier_w3();
+    if (K == 0 && emit) {
+      cx<T> vp = C.ih * dv + DV[t & 1][1][lane] + DV[t & 1][2][lane];
+      const T kq = bload<T>(C.RKAP, vr[2], zcl(t) * RBY);
+      vp += kq * PC;
+      if (RESID) vp = bload<cx<T>>(C.RB[3], vu[1], sc) - vp;
+      bstore(vp, C.RY[3], vu[1], sc);
+    }
+  };
+
+  for (int t = t0; t < C.z1; t += 2) {
+    step(t, UA, UB, WA, WB, MA, MB, PA, PB);
+    if (t + 1 < C.z1) step(t + 1, UB, UA, WB, WA, MB, MA, PB, PA);
+  }
+}
+
+template <typename T, bool RESID>
+__global__ void __launch_bounds__(WV_LANES * 3)
+k_apply3d_w3(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
+             int tiles_x, int nzc, int zc, int ntiles, int per_xcd) {
+  __shared__ cx<T> DV[2][3][WV_LANES];
+  const int bid = blockIdx.x;
+  const int tile = (bid & 7) * per_xcd + (bid >> 3);
+  if (tile >= ntiles) return;  // whole workgroup
+  int rest = tile;
+  const int tx = rest % tiles_x; rest /= tiles_x;
+  const int c2 = rest % L.n[1]; rest /= L.n[1];
+  const int tz = rest % nzc; rest /= nzc;
+  const int s = rest;
+  W3Ctx<T> C;
+  C.n1 = L.n[0]; C.n2 = L.n[1]; C.n3 = L.n[2];
+  C.plane = C.n1 * C.n2;
+  C.c1 = tx * WV_OUT - 1 + (int)threadIdx.x;
+  C.c2 = c2;
+  C.z0 = tz * zc;
+  C.z1 = min(C.z0 + zc, C.n3);
+  C.inx = C.c1 >= 0 && C.c1 < C.n1;
+  C.outlane = threadIdx.x >= 1 && threadIdx.x <= WV_OUT && C.inx;
+  const int cc1 = min(max(C.c1, 0), C.n1 - 1);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int rr = c2 - 2 + r;
+    C.rok[r] = rr >= 0 && rr < C.n2;
+    C.roff[r] = min(max(rr, 0), C.n2 - 1) * C.n1 + cc1;
+  }
+  C.offLc = c2 * C.n1 + max(cc1 - 1, 0);
+  const int64_t fs = L.fs;
+  const cx<T>* xs = x + (int64_t)s * L.vs;
+  cx<T>* ys = y + (int64_t)s * L.vs;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    C.RX[f] = rsrc(xs + f * fs, fs * (int64_t)sizeof(cx<T>));
+    C.RY[f] = rsrc(ys + f * fs, fs * (int64_t)sizeof(cx<T>));
+    C.RB[f] = RESID ? rsrc(b + (int64_t)s * L.vs + f * fs, fs * (int64_t)sizeof(cx<T>)) : C.RY[f];
+  }
+  C.RMU = rsrc(L.mu, fs * (int64_t)sizeof(T));
+  C.RRHO = rsrc(L.rho, fs * (int64_t)sizeof(T));
+  C.RKAP = rsrc(L.kap, fs * (int64_t)sizeof(T));
+  C.beta = L.beta; C.omb = T(1) - L.beta;
+  C.ih = L.ih; C.ih2 = L.ih * L.ih;
+  C.cn = C.omb / T(6);
+  C.omega2 = L.omega2;
+  C.has_abl = L.abl_w > T(0) && L.abl_amp != T(0);
+  C.h = L.h; C.len3 = C.n3 * L.h;
+  C.abl_w = L.abl_w; C.abl_iw = L.abl_iw; C.abl_amp = L.abl_amp;
+  const int k = threadIdx.y;
+  // gamma~ at this wave's faces: x_1 / x_2 parts of the layer (the face of
+  // u_k sits at a cell edge along x_k and at cell centres otherwise)
+  C.gf = L.gam;
+  if (C.has_abl) {
+    const T hf = T(0.5);
+    const T x1 = (k == 0 ? T(C.c1) : T(C.c1) + hf) * L.h;
+    const T x2 = (k == 1 ? T(c2) : T(c2) + hf) * L.h;
+    C.gf += absorb<T>(x1, C.n1 * L.h, L.abl_w, L.abl_iw, L.abl_amp) +
+            absorb<T>(x2, C.n2 * L.h, L.abl_w, L.abl_iw, L.abl_amp);
+  }
+  if (k == 0) w3_march<0, T, RESID>(C, DV);
+  else if (k == 1) w3_march<1, T, RESID>(C, DV);
+  else w3_march<2, T, RESID>(C, DV);
+}
+
+template <typename T>
+int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
+                      hipStream_t st) {
+  const int tiles_x = (L.n[0] + WV_OUT - 1) / WV_OUT;
+  if (L.fs * (int64_t)sizeof(cx<T>) > (int64_t)0x7fffffff) return (int)hipErrorInvalidValue;
+  if (zc <= 0) zc = 32;
+  {
+    const int64_t cols = (int64_t)tiles_x * L.n[1] * nrhs;
+    const int64_t want = (int64_t)L.n[2] * cols / 8192;
+    if (want < zc) zc = (int)(want < 4 ? 4 : want);
+  }
+  if (zc > L.n[2]) zc = L.n[2];
+  const int nzc = (L.n[2] + zc - 1) / zc;
+  const int64_t ntiles64 = (int64_t)tiles_x * L.n[1] * nzc * nrhs;
+  if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
+  const int ntiles = (int)ntiles64;
+  const int per_xcd = (ntiles + 7) / 8;
+  dim3 blk(WV_LANES, 3), grd(8 * per_xcd);
+  if (b)
+    hipLaunchKernelGGL((k_apply3d_w3<T, true>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b, (cx<T>*)y,
+                       tiles_x, nzc, zc, ntiles, per_xcd);
+  else
+    hipLaunchKernelGGL((k_apply3d_w3<T, false>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)nullptr,
+                       (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
+  return (int)hipGetLastError();
+}
+
+template int launch_apply3d_w3<double>(const LevelArgs<double>&, const void*, const void*, void*, int, int,
+                                       hipStream_t);
+template int launch_apply3d_w3<float>(const LevelArgs<float>&, const void*, const void*, void*, int, int,
+                                      hipStream_t);
+
+}  // namespace elh
