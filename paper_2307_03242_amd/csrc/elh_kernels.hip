@@ -196,6 +196,149 @@ __global__ void __launch_bounds__(256) k_vanka(LevelArgs<T> L, const cx<T>* __re
       if (ok[k][sd]) xs[idx[k][sd]] += w * (yr[k][sd] - yg[k][sd] * dp);
 }
 
+// 3D Vanka half-sweep with the block media formed from the 19 cells of the
+// 3x3x3 box around the cell that the blocks touch (corners excluded).  The
+// four edge means around a k-face between cells L and C sum to
+//   mu_L + mu_C + (1/4) (N4(L) + N4(C)),
+// N4(X) the sum of mu over the four neighbours of X across the axes other
+// than k (indices clamped to the grid, like the edge means of the
+// operator).  The absorbing-layer profile is summed per axis: centre and
+// both face positions once per cell.  Same blocks, Schur complement and
+// update as k_vanka.
+template <bool ADJ, typename T>
+__global__ void __launch_bounds__(256) k_vanka3(LevelArgs<T> L, const cx<T>* __restrict__ r, cx<T>* __restrict__ x,
+                                                 int colour, T w, int nrhs) {
+  // 32-bit index arithmetic (the launcher checks the cell count fits)
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  const int n0 = L.n[0], n1 = L.n[1];
+  const int half = (n0 + 1) / 2;
+  const int lines = n1 * L.n[2];
+  if (id >= lines * half || s >= nrhs) return;
+  const int line = id / half;
+  int c[3];
+  c[1] = line % n1;
+  c[2] = line / n1;
+  const int par = (colour + c[1] + c[2]) & 1;
+  c[0] = 2 * (id - line * half) + par;
+  if (c[0] >= n0) return;
+  const int64_t cell = (int64_t)line * n0 + c[0];
+  const int64_t st[3] = {1, n0, (int64_t)n0 * n1};
+  // clamped neighbour coordinates and their offsets from the cell
+  int64_t om[3], op[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    om[a] = c[a] > 0 ? -st[a] : 0;
+    op[a] = c[a] < L.n[a] - 1 ? st[a] : 0;
+  }
+  const T* __restrict__ M = L.mu + cell;
+  const T mc = M[0];
+  const T mx0 = M[om[0]], mx1 = M[op[0]], my0 = M[om[1]], my1 = M[op[1]], mz0 = M[om[2]], mz1 = M[op[2]];
+  const T mxy00 = M[om[0] + om[1]], mxy01 = M[om[0] + op[1]], mxy10 = M[op[0] + om[1]], mxy11 = M[op[0] + op[1]];
+  const T mxz00 = M[om[0] + om[2]], mxz01 = M[om[0] + op[2]], mxz10 = M[op[0] + om[2]], mxz11 = M[op[0] + op[2]];
+  const T myz00 = M[om[1] + om[2]], myz01 = M[om[1] + op[2]], myz10 = M[op[1] + om[2]], myz11 = M[op[1] + op[2]];
+  // N4 over the axes other than k at L = c - e_k, C = c, R = c + e_k
+  T n4[3][3];
+  n4[0][0] = mxy00 + mxy01 + mxz00 + mxz01;
+  n4[0][1] = my0 + my1 + mz0 + mz1;
+  n4[0][2] = mxy10 + mxy11 + mxz10 + mxz11;
+  n4[1][0] = mxy00 + mxy10 + myz00 + myz01;
+  n4[1][1] = mx0 + mx1 + mz0 + mz1;
+  n4[1][2] = mxy01 + mxy11 + myz10 + myz11;
+  n4[2][0] = mxz00 + mxz10 + myz00 + myz10;
+  n4[2][1] = mx0 + mx1 + my0 + my1;
+  n4[2][2] = mxz01 + mxz11 + myz01 + myz11;
+  const T mL[3] = {mx0, my0, mz0}, mR[3] = {mx1, my1, mz1};
+  const T* __restrict__ RH = L.rho + cell;
+  const T rc = RH[0];
+  const T rL[3] = {RH[om[0]], RH[om[1]], RH[om[2]]}, rR[3] = {RH[op[0]], RH[op[1]], RH[op[2]]};
+  // absorbing layer per axis: at the cell centre and at both faces
+  T acen[3] = {T(0), T(0), T(0)}, alo[3] = {T(0), T(0), T(0)}, ahi[3] = {T(0), T(0), T(0)};
+  if (L.abl_w > T(0) && L.abl_amp != T(0)) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T len = L.n[a] * L.h;
+      auto prof = [&](T xp) {
+        T d = (L.abl_w - xp > T(0) ? L.abl_w - xp : T(0)) + (xp - (len - L.abl_w) > T(0) ? xp - (len - L.abl_w) : T(0));
+        T q = d * L.abl_iw;
+        return L.abl_amp * (q * q);
+      };
+      acen[a] = prof((T(c[a]) + T(0.5)) * L.h);
+      alo[a] = prof(T(c[a]) * L.h);
+      ahi[a] = prof(T(c[a] + 1) * L.h);
+    }
+  }
+  const T asum = acen[0] + acen[1] + acen[2];
+  const cx<T>* rs = r + s * L.vs;
+  cx<T>* xs = x + s * L.vs;
+  const T s0 = L.beta + (T(1) - L.beta) / T(4);
+  const T s1 = (T(1) - L.beta) * T(0.125);
+  const T ih2 = L.ih * L.ih;
+  const T cn = (T(1) - L.beta) / T(6);
+  cx<T> yr[3][2], yg[3][2];
+  cx<T> schur = mk(L.kap[cell], T(0));
+  cx<T> rp = rs[3 * L.fs + cell];
+  int64_t idx[3][2];
+  bool ok[3][2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    ok[k][0] = c[k] >= 1;
+    ok[k][1] = c[k] + 1 <= L.n[k] - 1;
+    const T se0 = mL[k] + mc + T(0.25) * (n4[k][0] + n4[k][1]);
+    const T se1 = mc + mR[k] + T(0.25) * (n4[k][1] + n4[k][2]);
+    const T rf0 = T(0.5) * (rL[k] + rc), rf1 = T(0.5) * (rc + rR[k]);
+    const T at = asum - acen[k];
+    const cx<T> mf0 = mk(L.omega2, -L.omega2 * (L.gam + alo[k] + at));
+    const cx<T> mf1 = mk(L.omega2, -L.omega2 * (L.gam + ahi[k] + at));
+    cx<T> B[4];
+    B[0] = ok[k][0] ? mk(s0 * ih2 * (mL[k] + mc + se0), T(0)) - (L.beta * rf0) * mf0 : mk(T(1), T(0));
+    B[3] = ok[k][1] ? mk(s0 * ih2 * (mc + mR[k] + se1), T(0)) - (L.beta * rf1) * mf1 : mk(T(1), T(0));
+    if (ok[k][0] && ok[k][1]) {
+      B[1] = mk(-mc * s0 * ih2 + s1 * ih2 * se0, T(0)) - (cn * rf1) * mf0;
+      B[2] = mk(-mc * s0 * ih2 + s1 * ih2 * se1, T(0)) - (cn * rf0) * mf1;
+    } else {
+      B[1] = czero<T>();
+      B[2] = czero<T>();
+    }
+    idx[k][0] = k * L.fs + cell;
+    idx[k][1] = ok[k][1] ? k * L.fs + cell + st[k] : 0;
+    cx<T> g[2], d[2];
+    g[0] = mk(ok[k][0] ? L.ih : T(0), T(0));
+    g[1] = mk(ok[k][1] ? -L.ih : T(0), T(0));
+    d[0] = mk(ok[k][0] ? -s0 * L.ih : T(0), T(0));
+    d[1] = mk(ok[k][1] ? s0 * L.ih : T(0), T(0));
+    if (ADJ) {  // block of H^H = conjugate transpose
+      cx<T> t = B[1];
+      B[0] = conj(B[0]); B[3] = conj(B[3]);
+      B[1] = conj(B[2]); B[2] = conj(t);
+      cx<T> g0 = g[0], g1 = g[1];
+      g[0] = conj(d[0]); g[1] = conj(d[1]);
+      d[0] = conj(g0); d[1] = conj(g1);
+    }
+    cx<T> rk[2];
+    rk[0] = ok[k][0] ? rs[idx[k][0]] : czero<T>();
+    rk[1] = ok[k][1] ? rs[idx[k][1]] : czero<T>();
+    const cx<T> det = B[0] * B[3] - B[1] * B[2];
+    const T id2 = T(1) / abs2(det);
+    const cx<T> rdet = mk(det.re * id2, -det.im * id2);
+    const cx<T> inv00 = B[3] * rdet, inv01 = -(B[1] * rdet), inv10 = -(B[2] * rdet), inv11 = B[0] * rdet;
+    yr[k][0] = inv00 * rk[0] + inv01 * rk[1];
+    yr[k][1] = inv10 * rk[0] + inv11 * rk[1];
+    yg[k][0] = inv00 * g[0] + inv01 * g[1];
+    yg[k][1] = inv10 * g[0] + inv11 * g[1];
+    rp -= d[0] * yr[k][0] + d[1] * yr[k][1];
+    schur -= d[0] * yg[k][0] + d[1] * yg[k][1];
+  }
+  const T is2 = T(1) / abs2(schur);
+  const cx<T> dp = rp * mk(schur.re * is2, -schur.im * is2);
+  xs[3 * L.fs + cell] += w * dp;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+      if (ok[k][sd]) xs[idx[k][sd]] += w * (yr[k][sd] - yg[k][sd] * dp);
+}
+
 template <typename T>
 int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* x, int colour, double w, int nrhs,
                  hipStream_t st) {
@@ -204,8 +347,9 @@ int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* 
   const cx<T>* rp = (const cx<T>*)r;
   cx<T>* xp = (cx<T>*)x;
   if (dim == 3) {
-    if (adj) hipLaunchKernelGGL((k_vanka<3, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
-    else hipLaunchKernelGGL((k_vanka<3, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    if (work > 0x7fffffffll || L.fs > 0x7fffffffll) return (int)hipErrorInvalidValue;
+    if (adj) hipLaunchKernelGGL((k_vanka3<true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else hipLaunchKernelGGL((k_vanka3<false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
   } else {
     if (adj) hipLaunchKernelGGL((k_vanka<2, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
     else hipLaunchKernelGGL((k_vanka<2, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
@@ -315,6 +459,78 @@ __global__ void __launch_bounds__(256) k_prolong_add(LevelArgs<T> F, LevelArgs<T
   }
 }
 
+// 3D prolongation-add with fixed 2x2x2 coarse stencils: every axis takes two
+// coarse indices (clamped to the coarse grid) and weights that are zero
+// where the variable-length stencil of k_prolong_add has no term, so the
+// loop nest has no data-dependent trip counts.  Same weights as
+// k_prolong_add: linear along the face normal (coincident fine faces take
+// the coarse face, odd faces the mean of the two beside them, boundary
+// coarse faces contribute zero), 3/4 - 1/4 across cells.
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong3(LevelArgs<T> F, LevelArgs<T> C, const cx<T>* __restrict__ e,
+                                                   cx<T>* __restrict__ x, int nrhs) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (cell >= F.fs || s >= nrhs) return;
+  int i[3];
+  i[0] = cell % F.n[0];
+  const int t = cell / F.n[0];
+  i[1] = t % F.n[1];
+  i[2] = t / F.n[1];
+  const int cs[3] = {1, C.n[0], C.n[0] * C.n[1]};
+  // per axis: coarse offsets and weights of the cell stencil (c) and of the
+  // face-normal stencil (f)
+  int oc[3][2], of[3][2];
+  T wc[3][2], wf[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int I = i[a] >> 1;
+    const int I2 = (i[a] & 1) ? I + 1 : I - 1;
+    const bool ok2 = I2 >= 0 && I2 < C.n[a];
+    oc[a][0] = I * cs[a];
+    oc[a][1] = (ok2 ? I2 : I) * cs[a];
+    wc[a][0] = T(0.75);
+    wc[a][1] = ok2 ? T(0.25) : T(0);
+    int J0, J1;
+    T v0, v1;
+    if ((i[a] & 1) == 0) {
+      J0 = J1 = I;
+      v0 = T(1);
+      v1 = T(0);
+    } else {
+      J0 = I;
+      J1 = I + 1;
+      v0 = v1 = T(0.5);
+    }
+    const bool ok0 = J0 >= 1 && J0 <= C.n[a] - 1, ok1 = J1 >= 1 && J1 <= C.n[a] - 1;
+    of[a][0] = min(J0, C.n[a] - 1) * cs[a];
+    of[a][1] = min(J1, C.n[a] - 1) * cs[a];
+    wf[a][0] = ok0 ? v0 : T(0);
+    wf[a][1] = ok1 ? v1 : T(0);
+  }
+  const cx<T>* es = e + s * C.vs;
+  cx<T>* xs = x + s * F.vs;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    if (f < 3 && i[f] == 0) continue;  // boundary face stays zero
+    const cx<T>* ef = es + (int64_t)f * C.fs;
+    cx<T> acc = czero<T>();
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int a1 = 0; a1 < 2; ++a1)
+#pragma unroll
+        for (int a0 = 0; a0 < 2; ++a0) {
+          const int o = (f == 0 ? of[0][a0] : oc[0][a0]) + (f == 1 ? of[1][a1] : oc[1][a1]) +
+                        (f == 2 ? of[2][a2] : oc[2][a2]);
+          const T wgt = (f == 0 ? wf[0][a0] : wc[0][a0]) * (f == 1 ? wf[1][a1] : wc[1][a1]) *
+                        (f == 2 ? wf[2][a2] : wc[2][a2]);
+          acc += wgt * ef[o];
+        }
+    xs[(int64_t)f * F.fs + cell] += acc;
+  }
+}
+
 template <typename T>
 int launch_restrict(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* r, void* rc, int nrhs,
                     hipStream_t st) {
@@ -329,7 +545,9 @@ template <typename T>
 int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* e, void* x, int nrhs,
                        hipStream_t st) {
   dim3 blk(256), grd((unsigned)((F.fs + 255) / 256), nrhs);
-  if (dim == 3)
+  if (dim == 3 && F.fs <= 0x7fffffffll)
+    hipLaunchKernelGGL((k_prolong3<T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
+  else if (dim == 3)
     hipLaunchKernelGGL((k_prolong_add<3, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
   else
     hipLaunchKernelGGL((k_prolong_add<2, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
