@@ -429,20 +429,30 @@ static int scale_copy(elh_handle* H, const std::vector<zd>* a, const void* x, in
 
 
 // AZ: w = A z (z in TZ, w in T); AR: r = b - A x (T vectors);
-// M: z = M v (v in T, z in TZ).  Right-preconditioned flexible GMRES(m),
+// M: z = M v (v in TZ, z in TZ).  Right-preconditioned flexible GMRES(m),
 // zero initial guess, classical Gram-Schmidt, complex Givens rotations.
+//
+// The basis is kept unnormalised: V_i holds v_i / sig_i (sig_i = 1/||V_i||
+// kept per rhs on the host) and Z_i = M V_i, so that
+//   A M v_j = sig_j A Z_j,  h_ij = sig_i sig_j <V_i, A Z_j>,
+//   V_{j+1} = A Z_j - sum_i sig_i^2 <V_i, A Z_j> V_i,
+//   h_{j+1,j} = sig_j ||V_{j+1}||,  x += sum_j (y_j sig_j) Z_j.
+// A Z_j is written straight into V_{j+1}; the Gram-Schmidt update, its
+// norm and (when TZ != T) the TZ copy that feeds the next preconditioner
+// application (cyc_in) come out of one pass.  No vector is rescaled.
 template <typename T, typename TZ, typename OpAZ, typename OpAR, typename OpM>
 static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, OpAR AR, OpM M, const void* b,
-                 void* x, int restart, int maxit, double rtol, GmresStats& st_out) {
+                 void* x, int restart, int maxit, double rtol, GmresStats& st_out, void* cyc_in) {
   typedef cx<T> CT;
   typedef cx<TZ> CZ;
+  const bool cast_in = sizeof(TZ) != sizeof(T);
+  if (cast_in && !cyc_in) return fail(ELH_ERR_STATE, "mixed-precision GMRES needs a preconditioner input buffer");
   const int m = restart;
   const size_t vbytes = (size_t)nrhs * len * sizeof(CT);
   const size_t zbytes = (size_t)nrhs * len * sizeof(CZ);
-  if (ensure(ws.V, vbytes * (m + 1)) || ensure(ws.Z, zbytes * m) || ensure(ws.w, vbytes)) return ELH_ERR_OOM;
+  if (ensure(ws.V, vbytes * (m + 1)) || ensure(ws.Z, zbytes * m)) return ELH_ERR_OOM;
   CT* V = (CT*)ws.V.p;
   CZ* Z = (CZ*)ws.Z.p;
-  CT* w = (CT*)ws.w.p;
   const int64_t vstr = (int64_t)nrhs * len;  // stride between basis vectors
   hipStream_t st = H->st;
   std::vector<zd> dots;
@@ -451,9 +461,9 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
   CHK(fetch_dots(H, nrhs, 1, dots));
   std::vector<double> nb(nrhs), beta(nrhs);
   for (int s = 0; s < nrhs; ++s) nb[s] = sqrt(dots[s].real());
-  // x = 0, r = b
+  // x = 0, V_0 = r = b
   CHK(launch_zero(x, vbytes, st));
-  HIPCHK(hipMemcpyAsync(w, b, vbytes, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(V, b, vbytes, hipMemcpyDeviceToDevice, st));
   for (int s = 0; s < nrhs; ++s) beta[s] = nb[s];
   st_out.iters.assign(nrhs, 0);
   st_out.restarts.assign(nrhs, 0);
@@ -474,49 +484,52 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
   }
   int iters = 0;
   std::vector<zd> Hm((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), sn((size_t)nrhs * m), coef;
-  std::vector<double> cs((size_t)nrhs * m);
+  std::vector<double> cs((size_t)nrhs * m), sig((size_t)nrhs * (m + 1));
   std::vector<int> jend(nrhs);
   std::vector<char> live(nrhs);
   while (nact > 0 && iters < maxit) {
-    // V_0 = r / beta
-    coef.assign(nrhs, zd(0, 0));
-    for (int s = 0; s < nrhs; ++s)
-      if (active[s]) coef[s] = zd(1.0 / beta[s], 0);
-    CHK((scale_copy<CT, CT>(H, &coef, w, len, V, len, len, nrhs)));
     for (int s = 0; s < nrhs; ++s) {
+      sig[(size_t)s * (m + 1)] = active[s] ? 1.0 / beta[s] : 0.0;
       for (int i = 0; i <= m; ++i) g[s * (m + 1) + i] = 0;
       g[s * (m + 1)] = beta[s];
       jend[s] = -1;
       live[s] = active[s];
     }
+    if (cast_in) CHK((launch_scale_copy<CT, CZ>(nullptr, V, len, cyc_in, len, len, nrhs, st)));
     int j;
     for (j = 0; j < m; ++j) {
-      CHK(M((const void*)(V + j * vstr), (void*)(Z + j * vstr)));
-      CHK(AZ((const void*)(Z + j * vstr), (void*)w));
+      CHK(M(cast_in ? (const void*)cyc_in : (const void*)(V + j * vstr), (void*)(Z + j * vstr)));
+      CT* W = V + (j + 1) * vstr;
+      CHK(AZ((const void*)(Z + j * vstr), (void*)W));
       ++iters;
-      // classical Gram-Schmidt: h = V^H w, w -= V h
-      CHK((launch_multidot<CT, CT>(j + 1, V, vstr, len, w, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p,
+      // classical Gram-Schmidt on the unnormalised basis
+      CHK((launch_multidot<CT, CT>(j + 1, V, vstr, len, W, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p,
                                    st)));
       CHK(fetch_dots(H, nrhs, j + 1, dots));
       coef.assign((size_t)nrhs * (j + 1), zd(0, 0));
       for (int s = 0; s < nrhs; ++s)
-        for (int i = 0; i <= j; ++i) coef[s * (j + 1) + i] = -dots[s * (j + 1) + i];
+        for (int i = 0; i <= j; ++i) {
+          const double si = sig[(size_t)s * (m + 1) + i];
+          coef[s * (j + 1) + i] = -(si * si) * dots[s * (j + 1) + i];
+        }
       CHK(push_coef(H, coef));
-      CHK((launch_multiaxpy<CT, CT>(j + 1, (const double*)H->coef.p, V, vstr, len, w, len, len, nrhs, st)));
-      std::vector<zd> hcol = dots;
-      CHK((launch_multidot<CT, CT>(1, w, 0, len, w, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p, st)));
+      std::vector<zd> d = dots;
+      CHK((launch_axpy_norm<CT, CZ>(j + 1, (const double*)H->coef.p, V, vstr, len, W, len,
+                                    cast_in ? cyc_in : nullptr, len, len, nrhs, (double*)H->part.p,
+                                    (double*)H->dots.p, st)));
       CHK(fetch_dots(H, nrhs, 1, dots));
-      coef.assign(nrhs, zd(0, 0));
       bool any_live = false;
       for (int s = 0; s < nrhs; ++s) {
+        const double sj = sig[(size_t)s * (m + 1) + j];
+        const double wn = sqrt(dots[s].real());
+        sig[(size_t)s * (m + 1) + j + 1] = wn > 0 ? 1.0 / wn : 0.0;
         if (!live[s]) continue;
         st_out.iters[s]++;
-        double hn = sqrt(dots[s].real());
+        double hn = sj * wn;
         if (!isfinite(hn)) return fail(ELH_ERR_NUMERIC, "non-finite norm in GMRES (rhs %d)", s);
         zd* hc = &Hm[(size_t)s * (m + 1) * m];
-        for (int i = 0; i <= j; ++i) hc[i * m + j] = hcol[s * (j + 1) + i];
+        for (int i = 0; i <= j; ++i) hc[i * m + j] = (sig[(size_t)s * (m + 1) + i] * sj) * d[s * (j + 1) + i];
         hc[(j + 1) * m + j] = hn;
-        coef[s] = hn > 0 ? zd(1.0 / hn, 0) : zd(0, 0);
         // apply previous rotations
         for (int i = 0; i < j; ++i) {
           zd a = hc[i * m + j], bb = hc[(i + 1) * m + j];
@@ -551,13 +564,12 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
         if (res <= rtol || hn == 0) live[s] = 0;
         if (live[s]) any_live = true;
       }
-      CHK((scale_copy<CT, CT>(H, &coef, w, len, V + (j + 1) * vstr, len, len, nrhs)));
       if (!any_live || iters >= maxit) {
         ++j;
         break;
       }
     }
-    // y = H^{-1} g per rhs, then x += Z y
+    // y = H^{-1} g per rhs, then x += sum_j (y_j sig_j) Z_j
     int kmax = j;
     coef.assign((size_t)nrhs * kmax, zd(0, 0));
     for (int s = 0; s < nrhs; ++s) {
@@ -571,13 +583,13 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
         for (int q = i + 1; q < k; ++q) acc -= hc[i * m + q] * y[q];
         y[i] = acc / hc[i * m + i];
       }
-      for (int i = 0; i < k; ++i) coef[(size_t)s * kmax + i] = y[i];
+      for (int i = 0; i < k; ++i) coef[(size_t)s * kmax + i] = y[i] * sig[(size_t)s * (m + 1) + i];
     }
     CHK(push_coef(H, coef));
     CHK((launch_multiaxpy<CZ, CT>(kmax, (const double*)H->coef.p, Z, vstr, len, x, len, len, nrhs, st)));
-    // true residual r = b - A x
-    CHK(AR((const void*)x, b, (void*)w));
-    CHK((launch_multidot<CT, CT>(1, w, 0, len, w, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p, st)));
+    // true residual r = b - A x, the next V_0
+    CHK(AR((const void*)x, b, (void*)V));
+    CHK((launch_multidot<CT, CT>(1, V, 0, len, V, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p, st)));
     CHK(fetch_dots(H, nrhs, 1, dots));
     nact = 0;
     for (int s = 0; s < nrhs; ++s) {
@@ -706,7 +718,7 @@ static int coarse_solve(elh_handle* H, bool adj, const void* b, void* x, int nrh
     return gmres_device<T>(H, H->kin[prec], L.vs, nrhs, AZ, AR, M, b, x, d.coarse_restart, d.coarse_maxit);
   GmresStats gs;
   int rc = gmres<T, T>(H, H->kin[prec], L.vs, nrhs, AZ, AR, M, b, x, d.coarse_restart, d.coarse_maxit,
-                       d.coarse_rtol, gs);
+                       d.coarse_rtol, gs, nullptr);
   return rc < 0 ? rc : 0;
 }
 
@@ -927,25 +939,28 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
       return graphs_ok(H) ? run_graph(H, 0, adj, nrhs, v, z, fn) : fn();
     };
     rc = gmres<double, double>(H, H->kout[0], len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol,
-                               gs);
+                               gs, nullptr);
   } else {
-    // float32 cycle (Section 5.3 mixed precision): v is cast to float32,
-    // the cycle writes z_j in float32, the outer operator and all Krylov
-    // state stay float64.
+    // float32 cycle (Section 5.3 mixed precision): the cycle reads a
+    // float32 copy of the basis vector (written by the Gram-Schmidt pass)
+    // and writes z_j in float32; the outer operator reads z_j in float32
+    // and computes in float64; all Krylov state stays float64.
     KrylovWS& ws = H->kout[1];
-    if (ensure(ws.t, (size_t)nrhs * len * 16)) return ELH_ERR_OOM;
     auto M = [&](const void* v, void* z) {
-      auto fn = [&]() {
-        CHK((launch_scale_copy<cx<double>, cx<float>>(nullptr, v, len, L0.b[1].p, len, len, nrhs, H->st)));
-        return cycle<float>(H, 0, adj, L0.b[1].p, z, nrhs);
-      };
+      auto fn = [&]() { return cycle<float>(H, 0, adj, v, z, nrhs); };
       return graphs_ok(H) ? run_graph(H, 1, adj, nrhs, v, z, fn) : fn();
     };
+    const bool direct = H->d.dim == 3 && !adj && H->stencil == 0 && L0.fs >= 16 * 16 * 16 &&
+                        L0.fs * 16 <= (int64_t)0x7fffffff;
+    if (!direct && ensure(ws.t, (size_t)nrhs * len * 16)) return ELH_ERR_OOM;
     auto AZ = [&](const void* zi, void* wo) {
+      if (direct) return launch_apply3d_w3<double, float>(largs<double>(H, 0, false), zi, nullptr, wo, nrhs,
+                                                         H->zchunk, H->st);
       CHK((launch_scale_copy<cx<float>, cx<double>>(nullptr, zi, len, ws.t.p, len, len, nrhs, H->st)));
       return op_apply<double>(H, 0, false, adj, ws.t.p, nullptr, wo, nrhs);
     };
-    rc = gmres<double, float>(H, ws, len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol, gs);
+    rc = gmres<double, float>(H, ws, len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol, gs,
+                              L0.b[1].p);
   }
   if (rc < 0) return rc;
   int worst = ELH_OK;

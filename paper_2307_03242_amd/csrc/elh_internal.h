@@ -27,7 +27,8 @@ int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, co
 // 3D forward apply / residual, component-split wavefront march: three
 // wavefronts per x_2 row (one per displacement component) marching along
 // x_3, DPP for x_1 neighbours, one LDS hand-off per plane for the p row.
-template <typename T>
+// x holds complex TI (TI = T, or float with T = double); b, y complex T.
+template <typename T, typename TI = T>
 int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
                       hipStream_t st);
 template <typename T>
@@ -42,6 +43,12 @@ int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_r
 template <typename TV, typename TW>
 int launch_multiaxpy(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
                      int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st);
+// w += sum_i coef_i V_i in place with ||w||^2 per rhs into out[2s] (part:
+// scratch of RED_BLOCKS*2 doubles per rhs); f (optional) receives w in TF.
+template <typename TV, typename TF>
+int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
+                     int64_t wstride_rhs, void* f, int64_t fstride_rhs, int64_t len, int nrhs, double* part,
+                     double* out, hipStream_t st);
 template <typename TX, typename TY>
 int launch_scale_copy(const double* a, const void* x, int64_t xstride, void* y, int64_t ystride, int64_t len,
                       int nrhs, hipStream_t st);

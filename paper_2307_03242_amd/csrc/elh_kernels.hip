@@ -825,6 +825,86 @@ template int launch_multiaxpy<cx<float>, cx<double>>(int, const double*, const v
 template int launch_multiaxpy<cx<float>, cx<float>>(int, const double*, const void*, int64_t, int64_t, void*,
                                                     int64_t, int64_t, int, hipStream_t);
 
+// Gram-Schmidt update fused with its norm: w[s] += sum_i coef[s*m+i] V_i[s]
+// in place, part[] receives per-block partial sums of |w|^2 (entries 2b and
+// 2b+1, the second zero, so k_reduce_parts yields ||w||^2 as a complex
+// number), and when f is non-NULL the updated w is also written to f in
+// precision TF (the input of the next preconditioner application).
+template <typename TV, typename TF>
+__global__ void __launch_bounds__(RED_THREADS) k_axpy_norm(int m, const double* __restrict__ coef,
+                                                            const TV* __restrict__ V, int64_t vstride_vec,
+                                                            int64_t vstride_rhs, TV* __restrict__ w,
+                                                            int64_t wstride_rhs, TF* __restrict__ f,
+                                                            int64_t fstride_rhs, int64_t len,
+                                                            double* __restrict__ part) {
+  const int s = blockIdx.y;
+  double cr[MAXDOT], ci[MAXDOT];
+#pragma unroll
+  for (int i = 0; i < MAXDOT; ++i) {
+    cr[i] = i < m ? coef[(s * m + i) * 2] : 0.0;
+    ci[i] = i < m ? coef[(s * m + i) * 2 + 1] : 0.0;
+  }
+  double acc = 0.0;
+  TV* ws = w + s * wstride_rhs;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
+    auto wv = ws[t];
+    double re = (double)wv.re, im = (double)wv.im;
+#pragma unroll
+    for (int i = 0; i < MAXDOT; ++i) {
+      if (i < m) {
+        auto vv = V[i * vstride_vec + s * vstride_rhs + t];
+        const double vr = (double)vv.re, vi = (double)vv.im;
+        re += cr[i] * vr - ci[i] * vi;
+        im += cr[i] * vi + ci[i] * vr;
+      }
+    }
+    wv.re = re;
+    wv.im = im;
+    ws[t] = wv;
+    if (f) {
+      TF fv;
+      fv.re = re;
+      fv.im = im;
+      f[s * fstride_rhs + t] = fv;
+    }
+    acc += re * re + im * im;
+  }
+  __shared__ double red[RED_THREADS];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = RED_THREADS / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((int64_t)s * gridDim.x + blockIdx.x) * 2] = red[0];
+    part[((int64_t)s * gridDim.x + blockIdx.x) * 2 + 1] = 0.0;
+  }
+}
+
+template <typename TV, typename TF>
+int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
+                     int64_t wstride_rhs, void* f, int64_t fstride_rhs, int64_t len, int nrhs, double* part,
+                     double* out, hipStream_t st) {
+  if (m > MAXDOT) return (int)hipErrorInvalidValue;
+  int nb = (int)((len + RED_THREADS - 1) / RED_THREADS);
+  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL((k_axpy_norm<TV, TF>), dim3(nb, nrhs), dim3(RED_THREADS), 0, st, m, coef, (const TV*)V,
+                     vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(2, nrhs), dim3(256), 0, st, 2, nb, part, out);
+  return (int)hipGetLastError();
+}
+template int launch_axpy_norm<cx<double>, cx<float>>(int, const double*, const void*, int64_t, int64_t, void*,
+                                                     int64_t, void*, int64_t, int64_t, int, double*, double*,
+                                                     hipStream_t);
+template int launch_axpy_norm<cx<double>, cx<double>>(int, const double*, const void*, int64_t, int64_t, void*,
+                                                      int64_t, void*, int64_t, int64_t, int, double*, double*,
+                                                      hipStream_t);
+template int launch_axpy_norm<cx<float>, cx<float>>(int, const double*, const void*, int64_t, int64_t, void*,
+                                                    int64_t, void*, int64_t, int64_t, int, double*, double*,
+                                                    hipStream_t);
+
 // y[s] = a[s] * x[s]   (a complex double per rhs), with type conversion
 template <typename TX, typename TY>
 __global__ void __launch_bounds__(256) k_scale_copy(const double* __restrict__ a, const TX* __restrict__ x,

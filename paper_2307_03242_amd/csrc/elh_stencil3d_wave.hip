@@ -113,16 +113,19 @@ template <typename T> struct W3Ctx {
   T gf;         // gamma (+alpha) + x_1 and x_2 parts of the layer at this wave's faces
 };
 
-template <int K, typename T, bool RESID>
+template <int K, typename T, typename TI, bool RESID>
 __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
-  constexpr int CB = (int)sizeof(cx<T>), RBY = (int)sizeof(T);
+  constexpr int CB = (int)sizeof(cx<T>), CBI = (int)sizeof(cx<TI>), RBY = (int)sizeof(T);
   const T q = T(0.25), hf = T(0.5);
   const T beta = C.beta, omb = C.omb;
   const int lane = threadIdx.x;
   const int n3 = C.n3;
-  int vu[3], vr[4];
+  int vu[3], vi[3], vr[4];  // lane byte offsets: output/rhs fields, input fields, media
 #pragma unroll
-  for (int r = 0; r < 3; ++r) vu[r] = C.roff[r + 1] * CB;
+  for (int r = 0; r < 3; ++r) {
+    vu[r] = C.roff[r + 1] * CB;
+    vi[r] = C.roff[r + 1] * CBI;
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r) vr[r] = C.roff[r] * RBY;
   const int vrL = C.offLc * RBY;
@@ -136,16 +139,16 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
     return ok;
   };
 
-  // loads in flight for the next plane
-  cx<T> nu[3];
-  cx<T> npm, npc;
+  // loads in flight for the next plane (input precision TI)
+  cx<TI> nu[3];
+  cx<TI> npm, npc;
   T nmu[3], nrho[4], nrhoL;
   auto load_next = [&](int z) {
-    const int so = zcl(z) * CB, sr = zcl(z) * RBY;
+    const int so = zcl(z) * CBI, sr = zcl(z) * RBY;
 #pragma unroll
-    for (int r = 0; r < 3; ++r) nu[r] = bload<cx<T>>(C.RX[K], vu[r], so);
-    npc = bload<cx<T>>(C.RX[3], vu[1], so);
-    if (K == 1) npm = bload<cx<T>>(C.RX[3], vu[0], so);
+    for (int r = 0; r < 3; ++r) nu[r] = bload<cx<TI>>(C.RX[K], vi[r], so);
+    npc = bload<cx<TI>>(C.RX[3], vi[1], so);
+    if (K == 1) npm = bload<cx<TI>>(C.RX[3], vi[0], so);
     if (K == 1) {
       nmu[0] = bload<T>(C.RMU, vr[1], sr);
       nmu[1] = bload<T>(C.RMU, vr[2], sr);
@@ -196,9 +199,9 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
     // plane t+1: masked u, p and the media this component uses
     cx<T> Un[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) Un[r] = uok(r, tn) ? nu[r] : czero<T>();
-    const cx<T> Pnc = (C.inx && zok) ? npc : czero<T>();
-    const cx<T> Pnm = (K == 1 && C.inx && C.rok[1] && zok) ? npm : czero<T>();
+    for (int r = 0; r < 3; ++r) Un[r] = uok(r, tn) ? mk(T(nu[r].re), T(nu[r].im)) : czero<T>();
+    const cx<T> Pnc = (C.inx && zok) ? mk(T(npc.re), T(npc.im)) : czero<T>();
+    const cx<T> Pnm = (K == 1 && C.inx && C.rok[1] && zok) ? mk(T(npm.re), T(npm.im)) : czero<T>();
     T mun[3], rhon[3], rf[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -306,9 +309,9 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
   }
 }
 
-template <typename T, bool RESID>
+template <typename T, typename TI, bool RESID>
 __global__ void __launch_bounds__(WV_LANES * 3)
-k_apply3d_w3(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
+k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
              int tiles_x, int nzc, int zc, int ntiles, int per_xcd) {
   __shared__ cx<T> DV[2][3][WV_LANES];
   const int bid = blockIdx.x;
@@ -337,11 +340,11 @@ k_apply3d_w3(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __restric
   }
   C.offLc = c2 * C.n1 + max(cc1 - 1, 0);
   const int64_t fs = L.fs;
-  const cx<T>* xs = x + (int64_t)s * L.vs;
+  const cx<TI>* xs = x + (int64_t)s * L.vs;
   cx<T>* ys = y + (int64_t)s * L.vs;
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    C.RX[f] = rsrc(xs + f * fs, fs * (int64_t)sizeof(cx<T>));
+    C.RX[f] = rsrc(xs + f * fs, fs * (int64_t)sizeof(cx<TI>));
     C.RY[f] = rsrc(ys + f * fs, fs * (int64_t)sizeof(cx<T>));
     C.RB[f] = RESID ? rsrc(b + (int64_t)s * L.vs + f * fs, fs * (int64_t)sizeof(cx<T>)) : C.RY[f];
   }
@@ -366,12 +369,12 @@ k_apply3d_w3(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __restric
     C.gf += absorb<T>(x1, C.n1 * L.h, L.abl_w, L.abl_iw, L.abl_amp) +
             absorb<T>(x2, C.n2 * L.h, L.abl_w, L.abl_iw, L.abl_amp);
   }
-  if (k == 0) w3_march<0, T, RESID>(C, DV);
-  else if (k == 1) w3_march<1, T, RESID>(C, DV);
-  else w3_march<2, T, RESID>(C, DV);
+  if (k == 0) w3_march<0, T, TI, RESID>(C, DV);
+  else if (k == 1) w3_march<1, T, TI, RESID>(C, DV);
+  else w3_march<2, T, TI, RESID>(C, DV);
 }
 
-template <typename T>
+template <typename T, typename TI>
 int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
                       hipStream_t st) {
   const int tiles_x = (L.n[0] + WV_OUT - 1) / WV_OUT;
@@ -390,17 +393,20 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
   const int per_xcd = (ntiles + 7) / 8;
   dim3 blk(WV_LANES, 3), grd(8 * per_xcd);
   if (b)
-    hipLaunchKernelGGL((k_apply3d_w3<T, true>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b, (cx<T>*)y,
-                       tiles_x, nzc, zc, ntiles, per_xcd);
+    hipLaunchKernelGGL((k_apply3d_w3<T, TI, true>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)b,
+                       (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
   else
-    hipLaunchKernelGGL((k_apply3d_w3<T, false>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)nullptr,
+    hipLaunchKernelGGL((k_apply3d_w3<T, TI, false>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)nullptr,
                        (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
   return (int)hipGetLastError();
 }
 
-template int launch_apply3d_w3<double>(const LevelArgs<double>&, const void*, const void*, void*, int, int,
-                                       hipStream_t);
-template int launch_apply3d_w3<float>(const LevelArgs<float>&, const void*, const void*, void*, int, int,
-                                      hipStream_t);
-
+template int launch_apply3d_w3<double, double>(const LevelArgs<double>&, const void*, const void*, void*, int, int,
+                                               hipStream_t);
+template int launch_apply3d_w3<float, float>(const LevelArgs<float>&, const void*, const void*, void*, int, int,
+                                             hipStream_t);
+// float32 input, float64 arithmetic and output (the outer operator applied
+// to float32 preconditioned vectors)
+template int launch_apply3d_w3<double, float>(const LevelArgs<double>&, const void*, const void*, void*, int, int,
+                                              hipStream_t);
 }  // namespace elh
