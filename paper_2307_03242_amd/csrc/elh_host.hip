@@ -352,8 +352,10 @@ static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x,
   // the chip; small coarse levels use one thread per cell
   // (the wavefront march addresses a field with 32-bit byte offsets)
   const bool fits32 = H->lv[l].fs * (int64_t)sizeof(cx<T>) <= (int64_t)0x7fffffff;
-  if (H->d.dim == 3 && !adj && H->stencil == 0 && fits32 && H->lv[l].fs >= 16 * 16 * 16)
+  if (H->d.dim == 3 && H->stencil == 0 && fits32 && H->lv[l].fs >= 16 * 16 * 16) {
+    if (adj) return launch_apply3d_w3_adj<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
     return launch_apply3d_w3<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
+  }
   if (H->d.dim == 3 && !adj && H->stencil == 1 && H->lv[l].fs >= 24 * 24 * 24)
     return launch_apply3d_tiled<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->tile_y, H->st);
   return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);

@@ -31,6 +31,10 @@ int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, co
 template <typename T, typename TI = T>
 int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
                       hipStream_t st);
+// Same march for the adjoint H^H.
+template <typename T>
+int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
+                          hipStream_t st);
 template <typename T>
 int launch_apply3d_tiled(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc, int ty,
                          hipStream_t st);

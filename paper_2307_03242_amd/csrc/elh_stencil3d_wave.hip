@@ -109,9 +109,64 @@ template <typename T> struct W3Ctx {
   __amdgpu_buffer_rsrc_t RX[4], RY[4], RB[4], RMU, RRHO, RKAP;
   T beta, omb, ih, ih2, cn, omega2;
   bool has_abl;
-  T h, len3, abl_w, abl_iw, abl_amp;
+  T h, len1, len2, len3, abl_w, abl_iw, abl_amp, gam;
   T gf;         // gamma (+alpha) + x_1 and x_2 parts of the layer at this wave's faces
 };
+
+// Per-wavefront context of the march: tile coordinates, clamped row
+// offsets, buffer resources, constants, gamma~ of this wavefront's faces.
+template <typename T, typename TI, bool RESID>
+__device__ __forceinline__ void w3_setup(W3Ctx<T>& C, const LevelArgs<T>& L, const cx<TI>* __restrict__ x,
+                                         const cx<T>* __restrict__ b, cx<T>* __restrict__ y, int tx, int c2, int tz,
+                                         int zc, int s) {
+  const int k = threadIdx.y;
+  C.n1 = L.n[0]; C.n2 = L.n[1]; C.n3 = L.n[2];
+  C.plane = C.n1 * C.n2;
+  C.c1 = tx * WV_OUT - 1 + (int)threadIdx.x;
+  C.c2 = c2;
+  C.z0 = tz * zc;
+  C.z1 = min(C.z0 + zc, C.n3);
+  C.inx = C.c1 >= 0 && C.c1 < C.n1;
+  C.outlane = threadIdx.x >= 1 && threadIdx.x <= WV_OUT && C.inx;
+  const int cc1 = min(max(C.c1, 0), C.n1 - 1);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int rr = c2 - 2 + r;
+    C.rok[r] = rr >= 0 && rr < C.n2;
+    C.roff[r] = min(max(rr, 0), C.n2 - 1) * C.n1 + cc1;
+  }
+  C.offLc = c2 * C.n1 + max(cc1 - 1, 0);
+  const int64_t fs = L.fs;
+  const cx<TI>* xs = x + (int64_t)s * L.vs;
+  cx<T>* ys = y + (int64_t)s * L.vs;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    C.RX[f] = rsrc(xs + f * fs, fs * (int64_t)sizeof(cx<TI>));
+    C.RY[f] = rsrc(ys + f * fs, fs * (int64_t)sizeof(cx<T>));
+    C.RB[f] = RESID ? rsrc(b + (int64_t)s * L.vs + f * fs, fs * (int64_t)sizeof(cx<T>)) : C.RY[f];
+  }
+  C.RMU = rsrc(L.mu, fs * (int64_t)sizeof(T));
+  C.RRHO = rsrc(L.rho, fs * (int64_t)sizeof(T));
+  C.RKAP = rsrc(L.kap, fs * (int64_t)sizeof(T));
+  C.beta = L.beta; C.omb = T(1) - L.beta;
+  C.ih = L.ih; C.ih2 = L.ih * L.ih;
+  C.cn = C.omb / T(6);
+  C.omega2 = L.omega2;
+  C.has_abl = L.abl_w > T(0) && L.abl_amp != T(0);
+  C.h = L.h; C.len1 = C.n1 * L.h; C.len2 = C.n2 * L.h; C.len3 = C.n3 * L.h;
+  C.gam = L.gam;
+  C.abl_w = L.abl_w; C.abl_iw = L.abl_iw; C.abl_amp = L.abl_amp;
+  // gamma~ at this wave's faces: x_1 / x_2 parts of the layer (the face of
+  // u_k sits at a cell edge along x_k and at cell centres otherwise)
+  C.gf = L.gam;
+  if (C.has_abl) {
+    const T hf = T(0.5);
+    const T x1 = (k == 0 ? T(C.c1) : T(C.c1) + hf) * L.h;
+    const T x2 = (k == 1 ? T(c2) : T(c2) + hf) * L.h;
+    C.gf += absorb<T>(x1, C.n1 * L.h, L.abl_w, L.abl_iw, L.abl_amp) +
+            absorb<T>(x2, C.n2 * L.h, L.abl_w, L.abl_iw, L.abl_amp);
+  }
+}
 
 template <int K, typename T, typename TI, bool RESID>
 __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
@@ -309,6 +364,283 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
   }
 }
 
+// Adjoint (conjugate transpose) rows, same march.  For H^H the spread acts
+// after the flux: along each axis l the flux G_l = A_e(mu) D_l u (cell mu
+// when l = k) is formed at every flux point, spread by S_l over the other
+// two axes, and differenced along l.  The mass takes conj(omega^2 (1 - i
+// gamma~)) at each of the seven points and rho_f at the output face; the
+// coupling applies S_k to p before the difference; the p row is kappa p
+// plus the plain differences of the u_k.  Wavefront K keeps: u at planes t
+// and t+1 (rows c-1..c+1); A_2 G_1 at planes t-1, t; A_1 G_2 at the two
+// flux rows, planes t-1, t; the spread x_3 flux below plane t; the
+// attenuated u of the mass at (c, t-1), (c, t); the partial spreads of p.
+template <int K, typename T, bool RESID>
+__device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
+  constexpr int CB = (int)sizeof(cx<T>), RBY = (int)sizeof(T);
+  const T q = T(0.25), hf = T(0.5);
+  const T beta = C.beta, omb = C.omb;
+  const int lane = threadIdx.x;
+  const int n3 = C.n3;
+  int vu[3], vr[4], vl[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) vu[r] = C.roff[r + 1] * CB;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) vr[r] = C.roff[r] * RBY;
+  // the u_1 fluxes along x_2 and x_3 at lane 0 feed lane 1 through the
+  // spread, and their edge means need mu one cell to the left: load it
+  // rather than take it from the neighbouring lane
+  const int lshift = C.c1 > 0 && C.c1 <= C.n1 - 1 ? 1 : 0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) vl[r] = (C.roff[r + 1] - lshift) * RBY;
+  auto zcl = [&](int z) { return min(max(z, 0), n3 - 1) * C.plane; };
+  auto uok = [&](int r, int z) {
+    bool ok = C.inx && C.rok[r + 1] && z >= 0 && z < n3;
+    if (K == 0) ok = ok && C.c1 > 0;
+    if (K == 1) ok = ok && C.c2 - 1 + r > 0;
+    if (K == 2) ok = ok && z > 0;
+    return ok;
+  };
+  auto pok = [&](int r, int z) { return C.inx && C.rok[r + 1] && z >= 0 && z < n3; };
+  // attenuation gamma~ at this component's faces: x_1 / x_2 parts per row
+  // (rows c-1, c, c+1) and the x_3 part per plane
+  T gxy[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    gxy[r] = C.gam;
+    if (C.has_abl) {
+      const T x1 = (K == 0 ? T(C.c1) : T(C.c1) + hf) * C.h;
+      const T x2 = (K == 1 ? T(C.c2 - 1 + r) : T(C.c2 - 1 + r) + hf) * C.h;
+      gxy[r] += absorb<T>(x1, C.len1, C.abl_w, C.abl_iw, C.abl_amp) +
+                absorb<T>(x2, C.len2, C.abl_w, C.abl_iw, C.abl_amp);
+    }
+  }
+  auto a3of = [&](int z) {
+    if (!C.has_abl) return T(0);
+    return absorb<T>((K == 2 ? T(z) : T(z) + hf) * C.h, C.len3, C.abl_w, C.abl_iw, C.abl_amp);
+  };
+  auto att = [&](T g, cx<T> u) { return mk(u.re - g * u.im, u.im + g * u.re); };  // (1 + i g) u
+  auto A1 = [&](cx<T> v) { return q * (fromL(v) + fromR(v)) + hf * v; };
+
+  // loads in flight for the next plane
+  cx<T> nu[3], np[3];
+  T nmu[4], nrho[2], nmuL[3];
+  auto load_next = [&](int z) {
+    const int so = zcl(z) * CB, sr = zcl(z) * RBY;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) nu[r] = bload<cx<T>>(C.RX[K], vu[r], so);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (K != 1 || r < 2) np[r] = bload<cx<T>>(C.RX[3], vu[r], so);
+    if (K == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nmu[r] = bload<T>(C.RMU, vr[r], sr);
+      nrho[0] = bload<T>(C.RRHO, vr[1], sr);
+      nrho[1] = bload<T>(C.RRHO, vr[2], sr);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) nmu[r + 1] = bload<T>(C.RMU, vr[r + 1], sr);
+      nrho[1] = bload<T>(C.RRHO, vr[2], sr);
+    }
+    if (K == 0) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) nmuL[r] = bload<T>(C.RMU, vl[r], sr);
+    }
+  };
+
+  // windows
+  cx<T> UC[3];                 // u at (rows c-1..c+1, plane t)
+  cx<T> X1a, X1b, G1b;         // A_2 G_1 at t-1, t; G_1 at (c, t)
+  cx<T> Q2la, Q2lb, Q2ha, Q2hb, G2lb, G2hb;  // A_1 G_2 at the lower / upper flux row, t-1 and t; G_2 at t
+  cx<T> SG3;                   // spread x_3 flux through the face below plane t
+  cx<T> Wa, Wb;                // attenuated u at (c, t-1), (c, t)
+  cx<T> Pa0, Pb0, Pa1, Pb1, Pc0, Pc1;  // partial spreads of p (meaning depends on K)
+  T mub[4];                    // mu at plane t (rows c-2..c+1; K != 1 uses 1..3)
+  T mubL[3];                   // K == 0: mu one cell to the left at plane t (rows c-1..c+1)
+  T rhoa, rhob0, rhob1;        // rho: (c, t-1); plane t rows (K == 1: c-1, c; else c)
+  T a3a, a3b;                  // x_3 part of gamma~ at planes t-1, t
+  const int t0 = C.z0 - 2;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) UC[r] = czero<T>();
+  X1a = X1b = G1b = Q2la = Q2lb = Q2ha = Q2hb = G2lb = G2hb = SG3 = Wa = Wb = czero<T>();
+  Pa0 = Pb0 = Pa1 = Pb1 = Pc0 = Pc1 = czero<T>();
+  {
+    const int sr = zcl(t0) * RBY;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mub[r] = bload<T>(C.RMU, vr[r], sr);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) mubL[r] = K == 0 ? bload<T>(C.RMU, vl[r], sr) : T(0);
+    rhob0 = bload<T>(C.RRHO, vr[K == 1 ? 1 : 2], sr);
+    rhob1 = bload<T>(C.RRHO, vr[2], sr);
+    rhoa = rhob1;
+  }
+  a3a = a3b = a3of(t0);
+  load_next(t0 + 1);
+
+  for (int t = t0; t < C.z1; ++t) {
+    const int tn = t + 1;
+    const int sc = zcl(t) * CB;
+    cx<T> bq = czero<T>();
+    if (RESID) bq = bload<cx<T>>(C.RB[K], vu[1], sc);
+    // plane t+1, masked
+    cx<T> Un[3], Pn[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      Un[r] = uok(r, tn) ? nu[r] : czero<T>();
+      Pn[r] = (pok(r, tn) && (K != 1 || r < 2)) ? np[r] : czero<T>();
+    }
+    T mun[4], munL[3], rhon0, rhon1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mun[r] = (K == 1 || r > 0) ? nmu[r] : T(0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) munL[r] = K == 0 ? nmuL[r] : T(0);
+    rhon0 = K == 1 ? nrho[0] : nrho[1];
+    rhon1 = nrho[1];
+    const T a3n = a3of(tn);
+    load_next(t + 2);
+
+    // edge/cell mu of this component's fluxes at plane t+1 (and between t, t+1)
+    T mu1[3], mu2l, mu2h, mu3[3];
+    if (K == 0) {
+      T MXn[3], MXb[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        MXn[r] = hf * (munL[r] + mun[r + 1]);
+        MXb[r] = hf * (mubL[r] + mub[r + 1]);
+        mu1[r] = mun[r + 1];                 // cell mu (flux along x_1 of u_1)
+        mu3[r] = hf * (MXb[r] + MXn[r]);     // edges between planes t, t+1
+      }
+      mu2l = hf * (MXn[0] + MXn[1]);
+      mu2h = hf * (MXn[1] + MXn[2]);
+    } else if (K == 1) {
+      T MYn[3], MYb[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        MYn[r] = hf * (mun[r] + mun[r + 1]);
+        MYb[r] = hf * (mub[r] + mub[r + 1]);
+        mu1[r] = hf * (fromL(MYn[r]) + MYn[r]);
+        mu3[r] = hf * (MYb[r] + MYn[r]);
+      }
+      mu2l = mun[1];  // cell mu of rows c-1 and c (flux along x_2 of u_2)
+      mu2h = mun[2];
+    } else {
+      T MZn[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        MZn[r] = hf * (mub[r + 1] + mun[r + 1]);
+        mu1[r] = hf * (fromL(MZn[r]) + MZn[r]);
+        mu3[r] = mub[r + 1];  // cell mu of plane t (flux along x_3 of u_3)
+      }
+      mu2l = hf * (MZn[0] + MZn[1]);
+      mu2h = hf * (MZn[1] + MZn[2]);
+    }
+    // flux along x_1 at plane t+1 (lane x: cell x for u_1, edge x otherwise)
+    cx<T> G1n[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) G1n[r] = mu1[r] * (K == 0 ? fromR(Un[r]) - Un[r] : Un[r] - fromL(Un[r]));
+    const cx<T> X1n = q * (G1n[0] + G1n[2]) + hf * G1n[1];
+    const cx<T> SG1 = beta * G1b + omb * (q * (X1a + X1n) + hf * X1b);
+    cx<T> acc = K == 0 ? fromL(SG1) - SG1 : SG1 - fromR(SG1);
+    // flux along x_2 at the lower / upper flux row, plane t+1
+    const cx<T> G2ln = mu2l * (Un[1] - Un[0]), G2hn = mu2h * (Un[2] - Un[1]);
+    const cx<T> Q2ln = A1(G2ln), Q2hn = A1(G2hn);
+    const cx<T> SG2l = beta * G2lb + omb * (q * (Q2la + Q2ln) + hf * Q2lb);
+    const cx<T> SG2h = beta * G2hb + omb * (q * (Q2ha + Q2hn) + hf * Q2hb);
+    acc += SG2l - SG2h;
+    // flux along x_3 through the face between planes t and t+1
+    cx<T> G3[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) G3[r] = mu3[r] * (Un[r] - UC[r]);
+    const cx<T> V3 = q * (G3[0] + G3[2]) + hf * G3[1];
+    const cx<T> SG3n = beta * G3[1] + omb * A1(V3);
+    acc += SG3 - SG3n;
+    acc = C.ih2 * acc;
+    // adjoint spread mass: rho_f of the output face times the spread of
+    // (1 + i gamma~) u over the seven points
+    const cx<T> Wn = att(gxy[1] + a3n, Un[1]);
+    const cx<T> nb = fromL(Wb) + fromR(Wb) + att(gxy[0] + a3b, UC[0]) + att(gxy[2] + a3b, UC[2]) + Wa + Wn;
+    const cx<T> sm = beta * Wb + C.cn * nb;
+    T rfP;
+    if (K == 0) rfP = hf * (fromL(rhob1) + rhob1);
+    else if (K == 1) rfP = hf * (rhob0 + rhob1);
+    else rfP = hf * (rhoa + rhob1);
+    acc -= (C.omega2 * rfP) * sm;
+    // coupling: S_k p at the cells below and above the face, differenced
+    cx<T> dv;
+    if (K == 0) {
+      const cx<T> A2n = q * (Pn[0] + Pn[2]) + hf * Pn[1];
+      const cx<T> SP = beta * Pc0 + omb * (q * (Pa0 + A2n) + hf * Pb0);
+      acc += C.ih * (fromL(SP) - SP);
+      dv = UC[1] - fromR(UC[1]);
+      Pa0 = Pb0; Pb0 = A2n; Pc1 = Pc0; Pc0 = Pn[1];  // Pc1: p(c, t) for the p row
+    } else if (K == 1) {
+      const cx<T> A1m = A1(Pn[0]), A1c = A1(Pn[1]);
+      const cx<T> SPm = beta * Pc0 + omb * (q * (Pa0 + A1m) + hf * Pb0);
+      const cx<T> SPc = beta * Pc1 + omb * (q * (Pa1 + A1c) + hf * Pb1);
+      acc += C.ih * (SPm - SPc);
+      dv = UC[1] - UC[2];
+      Pa0 = Pb0; Pb0 = A1m; Pa1 = Pb1; Pb1 = A1c; Pc0 = Pn[0]; Pc1 = Pn[1];
+    } else {
+      const cx<T> V = q * (Pn[0] + Pn[2]) + hf * Pn[1];
+      const cx<T> SPn = beta * Pn[1] + omb * A1(V);
+      acc += C.ih * (Pa0 - Pb0);
+      dv = UC[1] - Un[1];
+      Pa0 = Pb0; Pb0 = SPn;
+    }
+    const bool emit = C.outlane && t >= C.z0;
+    if (emit) {
+      const bool face = K == 0 ? C.c1 > 0 : (K == 1 ? C.c2 > 0 : t > 0);
+      cx<T> v = face ? acc : czero<T>();
+      if (RESID && face) v = bq - v;
+      bstore(v, C.RY[K], vu[1], sc);
+    }
+    DV[t & 1][K][lane] = C.ih * dv;
+    // advance the windows
+    X1a = X1b; X1b = X1n; G1b = G1n[1];
+    Q2la = Q2lb; Q2lb = Q2ln; Q2ha = Q2hb; Q2hb = Q2hn; G2lb = G2ln; G2hb = G2hn;
+    SG3 = SG3n;
+    Wa = Wb; Wb = Wn;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) UC[r] = Un[r];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mub[r] = mun[r];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) mubL[r] = munL[r];
+    rhoa = rhob1; rhob0 = rhon0; rhob1 = rhon1;
+    a3a = a3b; a3b = a3n;
+    lds_barrier_w3();
+    if (K == 0 && emit) {
+      // p row of cell (c1, c2, t): kappa p + the three differences
+      cx<T> vp = DV[t & 1][0][lane] + DV[t & 1][1][lane] + DV[t & 1][2][lane];
+      const T kq = bload<T>(C.RKAP, vr[2], zcl(t) * RBY);
+      vp += kq * Pc1;
+      if (RESID) vp = bload<cx<T>>(C.RB[3], vu[1], sc) - vp;
+      bstore(vp, C.RY[3], vu[1], sc);
+    }
+  }
+  (void)a3a;
+}
+
+template <typename T, bool RESID>
+__global__ void __launch_bounds__(WV_LANES * 3)
+k_apply3d_w3_adj(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
+                 int tiles_x, int nzc, int zc, int ntiles, int per_xcd) {
+  __shared__ cx<T> DV[2][3][WV_LANES];
+  const int bid = blockIdx.x;
+  const int tile = (bid & 7) * per_xcd + (bid >> 3);
+  if (tile >= ntiles) return;  // whole workgroup
+  int rest = tile;
+  const int tx = rest % tiles_x; rest /= tiles_x;
+  const int c2 = rest % L.n[1]; rest /= L.n[1];
+  const int tz = rest % nzc; rest /= nzc;
+  const int s = rest;
+  W3Ctx<T> C;
+  w3_setup<T, T, RESID>(C, L, x, b, y, tx, c2, tz, zc, s);
+  const int k = threadIdx.y;
+  if (k == 0) w3_march_adj<0, T, RESID>(C, DV);
+  else if (k == 1) w3_march_adj<1, T, RESID>(C, DV);
+  else w3_march_adj<2, T, RESID>(C, DV);
+}
+
 template <typename T, typename TI, bool RESID>
 __global__ void __launch_bounds__(WV_LANES * 3)
 k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
@@ -323,55 +655,21 @@ k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restri
   const int tz = rest % nzc; rest /= nzc;
   const int s = rest;
   W3Ctx<T> C;
-  C.n1 = L.n[0]; C.n2 = L.n[1]; C.n3 = L.n[2];
-  C.plane = C.n1 * C.n2;
-  C.c1 = tx * WV_OUT - 1 + (int)threadIdx.x;
-  C.c2 = c2;
-  C.z0 = tz * zc;
-  C.z1 = min(C.z0 + zc, C.n3);
-  C.inx = C.c1 >= 0 && C.c1 < C.n1;
-  C.outlane = threadIdx.x >= 1 && threadIdx.x <= WV_OUT && C.inx;
-  const int cc1 = min(max(C.c1, 0), C.n1 - 1);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int rr = c2 - 2 + r;
-    C.rok[r] = rr >= 0 && rr < C.n2;
-    C.roff[r] = min(max(rr, 0), C.n2 - 1) * C.n1 + cc1;
-  }
-  C.offLc = c2 * C.n1 + max(cc1 - 1, 0);
-  const int64_t fs = L.fs;
-  const cx<TI>* xs = x + (int64_t)s * L.vs;
-  cx<T>* ys = y + (int64_t)s * L.vs;
-#pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    C.RX[f] = rsrc(xs + f * fs, fs * (int64_t)sizeof(cx<TI>));
-    C.RY[f] = rsrc(ys + f * fs, fs * (int64_t)sizeof(cx<T>));
-    C.RB[f] = RESID ? rsrc(b + (int64_t)s * L.vs + f * fs, fs * (int64_t)sizeof(cx<T>)) : C.RY[f];
-  }
-  C.RMU = rsrc(L.mu, fs * (int64_t)sizeof(T));
-  C.RRHO = rsrc(L.rho, fs * (int64_t)sizeof(T));
-  C.RKAP = rsrc(L.kap, fs * (int64_t)sizeof(T));
-  C.beta = L.beta; C.omb = T(1) - L.beta;
-  C.ih = L.ih; C.ih2 = L.ih * L.ih;
-  C.cn = C.omb / T(6);
-  C.omega2 = L.omega2;
-  C.has_abl = L.abl_w > T(0) && L.abl_amp != T(0);
-  C.h = L.h; C.len3 = C.n3 * L.h;
-  C.abl_w = L.abl_w; C.abl_iw = L.abl_iw; C.abl_amp = L.abl_amp;
+  w3_setup<T, TI, RESID>(C, L, x, b, y, tx, c2, tz, zc, s);
   const int k = threadIdx.y;
-  // gamma~ at this wave's faces: x_1 / x_2 parts of the layer (the face of
-  // u_k sits at a cell edge along x_k and at cell centres otherwise)
-  C.gf = L.gam;
-  if (C.has_abl) {
-    const T hf = T(0.5);
-    const T x1 = (k == 0 ? T(C.c1) : T(C.c1) + hf) * L.h;
-    const T x2 = (k == 1 ? T(c2) : T(c2) + hf) * L.h;
-    C.gf += absorb<T>(x1, C.n1 * L.h, L.abl_w, L.abl_iw, L.abl_amp) +
-            absorb<T>(x2, C.n2 * L.h, L.abl_w, L.abl_iw, L.abl_amp);
-  }
   if (k == 0) w3_march<0, T, TI, RESID>(C, DV);
   else if (k == 1) w3_march<1, T, TI, RESID>(C, DV);
   else w3_march<2, T, TI, RESID>(C, DV);
+}
+
+// x_3 chunk length: at least ~8192 workgroups in flight on small grids
+static int w3_chunk(const int* n, int tiles_x, int nrhs, int zc) {
+  if (zc <= 0) zc = 32;
+  const int64_t cols = (int64_t)tiles_x * n[1] * nrhs;
+  const int64_t want = (int64_t)n[2] * cols / 8192;
+  if (want < zc) zc = (int)(want < 4 ? 4 : want);
+  if (zc > n[2]) zc = n[2];
+  return zc;
 }
 
 template <typename T, typename TI>
@@ -379,13 +677,7 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
                       hipStream_t st) {
   const int tiles_x = (L.n[0] + WV_OUT - 1) / WV_OUT;
   if (L.fs * (int64_t)sizeof(cx<T>) > (int64_t)0x7fffffff) return (int)hipErrorInvalidValue;
-  if (zc <= 0) zc = 32;
-  {
-    const int64_t cols = (int64_t)tiles_x * L.n[1] * nrhs;
-    const int64_t want = (int64_t)L.n[2] * cols / 8192;
-    if (want < zc) zc = (int)(want < 4 ? 4 : want);
-  }
-  if (zc > L.n[2]) zc = L.n[2];
+  zc = w3_chunk(L.n, tiles_x, nrhs, zc);
   const int nzc = (L.n[2] + zc - 1) / zc;
   const int64_t ntiles64 = (int64_t)tiles_x * L.n[1] * nzc * nrhs;
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
@@ -400,6 +692,31 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
                        (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
   return (int)hipGetLastError();
 }
+
+template <typename T>
+int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
+                          hipStream_t st) {
+  const int tiles_x = (L.n[0] + WV_OUT - 1) / WV_OUT;
+  if (L.fs * (int64_t)sizeof(cx<T>) > (int64_t)0x7fffffff) return (int)hipErrorInvalidValue;
+  zc = w3_chunk(L.n, tiles_x, nrhs, zc);
+  const int nzc = (L.n[2] + zc - 1) / zc;
+  const int64_t ntiles64 = (int64_t)tiles_x * L.n[1] * nzc * nrhs;
+  if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
+  const int ntiles = (int)ntiles64;
+  const int per_xcd = (ntiles + 7) / 8;
+  dim3 blk(WV_LANES, 3), grd(8 * per_xcd);
+  if (b)
+    hipLaunchKernelGGL((k_apply3d_w3_adj<T, true>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b,
+                       (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
+  else
+    hipLaunchKernelGGL((k_apply3d_w3_adj<T, false>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)nullptr,
+                       (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
+  return (int)hipGetLastError();
+}
+template int launch_apply3d_w3_adj<double>(const LevelArgs<double>&, const void*, const void*, void*, int, int,
+                                           hipStream_t);
+template int launch_apply3d_w3_adj<float>(const LevelArgs<float>&, const void*, const void*, void*, int, int,
+                                          hipStream_t);
 
 template int launch_apply3d_w3<double, double>(const LevelArgs<double>&, const void*, const void*, void*, int, int,
                                                hipStream_t);

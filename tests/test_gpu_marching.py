@@ -1,0 +1,120 @@
+"""GPU parity of the marching 3D kernels against the CPU oracle.
+
+The wavefront-march stencil (forward and adjoint, apply and residual, float64
+and float32 input), the 19-cell Vanka half-sweep and the fixed-stencil
+prolongation take over from the point-wise kernels from 16^3 cells up.  The
+shapes here span several 62-lane x_1 segments with a ragged last one,
+several x_3 chunks with a ragged last one and two right-hand sides, so every
+boundary case of the tiling is exercised.  Expected values come from
+`oracle` only.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import grid as G
+from oracle import operator as O
+from oracle import transfer as T
+from oracle import cycle as C
+from oracle.smoother import Vanka
+from synthetic import make_media, random_field, omega_for_ppw
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 3e-5
+# (n_3, n_2, n_1): n_1 = 70 and 130 give two and three x_1 segments of 62
+# lanes (the last one ragged); n_3 = 10, 17 and 18 give ragged x_3 chunks
+SHAPES = [(10, 12, 70), (17, 9, 130)]
+EVEN_SHAPES = [(10, 12, 70), (18, 10, 130)]  # two-level hierarchies
+
+
+def _setup(shape, seed=5, levels=1, alpha=0.3):
+    from paper_2307_03242_amd import Problem
+    m = make_media(shape, seed)
+    om = omega_for_ppw(m["vs"].min(), 1.0, 10)
+    abl = 3.0
+    prob = Problem(torch.from_numpy(m["lam"]), torch.from_numpy(m["mu"]), torch.from_numpy(m["rho"]),
+                   h=1.0, omega=om, gamma=0.01, alpha=alpha, beta=2 / 3, abl_width=abl, abl_amp=2.0,
+                   levels=levels, damping=(0.55, 0.35), coarse_mode="relax", coarse_sweeps=2)
+    lv = G.Level(tuple(reversed(shape)), 1.0, om, 0.01, 2 / 3, m["lam"], m["mu"], m["rho"],
+                 abl_width=abl, abl_amp=2.0)
+    return prob, lv
+
+
+def _dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().to(torch.complex128).numpy()
+
+
+def _maxrel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("shifted", [False, True])
+def test_marching_apply_and_residual(shape, adjoint, shifted):
+    prob, lv = _setup(shape)
+    shift = 0.3 if shifted else 0.0
+    x = random_field(shape, 11, nrhs=2)
+    b = random_field(shape, 12, nrhs=2)
+    ref = np.stack([O.apply(lv, x[s], shift=shift, adjoint=adjoint) for s in range(2)])
+    y = _host(prob.apply(_dev(x), shifted=shifted, adjoint=adjoint))
+    assert _maxrel(y, ref) <= TOL64
+    ref32 = np.stack([O.apply(lv, x[s].astype(np.complex64).astype(np.complex128), shift=shift, adjoint=adjoint)
+                      for s in range(2)])
+    y32 = _host(prob.apply(_dev(x, torch.complex64), shifted=shifted, adjoint=adjoint))
+    assert _maxrel(y32, ref32) <= TOL32
+    r = _host(prob.residual(_dev(b), _dev(x), shifted=shifted, adjoint=adjoint))
+    assert _maxrel(r, b - ref) <= TOL64
+    r32 = _host(prob.residual(_dev(b, torch.complex64), _dev(x, torch.complex64), shifted=shifted,
+                              adjoint=adjoint))
+    assert _maxrel(r32, b - ref) <= TOL32
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_marching_relax(shape, adjoint):
+    """residual + 19-cell Vanka half-sweeps of both colours on the shifted
+    operator, against the oracle's block smoother"""
+    prob, lv = _setup(shape)
+    A = O.assemble(lv, shift=0.3)
+    if adjoint:
+        A = A.conj().T.tocsr()
+    vk = Vanka(lv, A)
+    x = random_field(shape, 21, nrhs=1)[0]
+    b = random_field(shape, 22, nrhs=1)[0]
+    xg = _dev(x)
+    for colour in (0, 1):
+        prob.relax(_dev(b), xg, colour, adjoint=adjoint)
+        x = G.unpack(lv, vk.half_sweep(G.pack(lv, x), G.pack(lv, b), 0.55, colour))
+        assert _maxrel(_host(xg), x) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", EVEN_SHAPES)
+def test_marching_prolong_add(shape):
+    prob, lv = _setup(shape, levels=2)
+    lvc = C.coarsen_level(lv)
+    x = random_field(shape, 31, nrhs=2)
+    e = random_field(lvc.np_shape, 32, nrhs=2)
+    out = _host(prob.prolong_add(_dev(e), _dev(x)))
+    ref = np.stack([x[s] + T.prolong(lv, e[s], lvc) for s in range(2)])
+    assert _maxrel(out, ref) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", EVEN_SHAPES)
+def test_marching_vcycle_and_adjoint_vcycle(shape):
+    """one V-cycle (and one adjoint V-cycle) built from the marching kernels
+    against the oracle's cycle"""
+    prob, lv = _setup(shape, levels=2)
+    b = random_field(shape, 51, nrhs=1)
+    for adjoint in (False, True):
+        cp = C.CycleParams(levels=2, alpha=0.3, damping=(0.55, 0.35), coarse="relax", coarse_sweeps=2)
+        hier = C.Hierarchy(lv, cp, adjoint=adjoint)
+        ref = hier.vcycle_storage(b[0])
+        got = _host(prob.vcycle(_dev(b), adjoint=adjoint))[0]
+        assert _maxrel(got, ref) <= 1e-11
