@@ -28,6 +28,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak, GB/s
 APPLY_BYTES_F64 = 152      # algorithmic bytes per cell of one operator apply (x, y, mu, rho, kappa)
 APPLY_BYTES_F32 = 76
+RESID_BYTES_F32 = 108      # residual b - H_s x in complex64: x, b, y (32 B each) + mu, rho, kappa (float32)
+# HBM bytes per launch of the float32 residual at 256^3 from the rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes over `bench.py --pmc-target` (each scaled
+# by what the same counter reads for a 1 GiB device copy: x2.0 for FETCH_SIZE,
+# x1.0 for WRITE_SIZE): 1.484 GB read + 0.559 GB written.  Set to None when
+# the kernel changes until the passes are repeated.
+RESID_TRAFFIC_BYTES = 2.042e9
 
 
 def parse():
@@ -52,6 +59,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=64, help="oracle sample grid (cells per axis)")
     ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--pmc-target", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration) and the float32 residual at "
+                         "--n^3, three launches each, for rocprofv3 --pmc passes")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-sources, uneven-batch and gradient measurements")
     return ap.parse_args()
@@ -237,6 +247,22 @@ def main():
     rho = torch.from_numpy(m["rho"]).cuda()
     q = torch.from_numpy(point_source(shape)[None]).cuda()
     stream = torch.cuda.current_stream()
+    if args.pmc_target:
+        from synthetic import random_field
+        src = torch.ones(1 << 27, dtype=torch.complex64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        pr = Problem(lam, mu, rho, precond_dtype=torch.complex64, **cfg)
+        xx = torch.from_numpy(random_field(shape, 1)).cuda().to(torch.complex64)
+        bb = torch.from_numpy(random_field(shape, 2)).cuda().to(torch.complex64)
+        rr = torch.empty_like(xx)
+        for _ in range(3):
+            pr.residual(bb, xx, shifted=True, out=rr)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_target": True, "copy_bytes_each_way": 1 << 30, "n": n,
+                          "resid_algorithmic_bytes": RESID_BYTES_F32 * n ** 3}), flush=True)
+        return
 
     def timed_solves(prob):
         u = torch.empty_like(q)
@@ -260,7 +286,9 @@ def main():
     t32, info32, u32 = timed_solves(p32)
     rel_diff = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
 
-    # stencil apply bandwidth, HIP events on the stream the library uses
+    # stencil bandwidth, HIP events on the stream the library uses: the
+    # operator apply in both precisions, and the float32 residual on the
+    # shifted operator (the dominant kernel of the float32-cycle solve)
     from synthetic import random_field
     x = torch.from_numpy(random_field(shape, 1)).cuda()
     apply = {}
@@ -276,7 +304,19 @@ def main():
         ev1.synchronize()
         ms = ev0.elapsed_time(ev1) / args.apply_reps
         apply[name] = dict(ms=ms, gbs=nbytes * n ** 3 / (ms * 1e-3) / 1e9)
-    del x
+    xx = x.to(torch.complex64)
+    bb = torch.from_numpy(random_field(shape, 2)).cuda().to(torch.complex64)
+    rr = torch.empty_like(xx)
+    p32.residual(bb, xx, shifted=True, out=rr)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.apply_reps):
+        p32.residual(bb, xx, shifted=True, out=rr)
+    ev1.record(stream)
+    ev1.synchronize()
+    resid_ms = ev0.elapsed_time(ev1) / args.apply_reps
+    resid_gbs = RESID_BYTES_F32 * n ** 3 / (resid_ms * 1e-3) / 1e9
+    del x, xx, bb, rr
 
     value = 1.0 / t32
     it32 = int(np.median([i["iters"] for i in info32]))
@@ -310,9 +350,12 @@ def main():
         "speedup_fp32_vs_fp64": t64 / t32,
         "apply": {"f64_ms": apply["f64"]["ms"], "f64_GBps": apply["f64"]["gbs"],
                   "f32_ms": apply["f32"]["ms"], "f32_GBps": apply["f32"]["gbs"]},
-        "roofline": {"bound": "hbm", "achieved": apply["f64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": apply["f64"]["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "operator apply, complex128, %d^3 (152 B/cell)" % n},
+        "roofline": {"bound": "hbm", "achieved": resid_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": resid_gbs / HBM_PEAK_GBS,
+                     "traffic": (RESID_TRAFFIC_BYTES / (resid_ms * 1e-3) / 1e9
+                                 if RESID_TRAFFIC_BYTES and n == 256 else None),
+                     "kernel": "residual b - H_s x, complex64, %d^3 (%d B/cell), %.3f ms per launch"
+                               % (n, RESID_BYTES_F32, resid_ms)},
     }
     del p32
     torch.cuda.empty_cache()

@@ -116,6 +116,15 @@ class Problem:
             return t.shape[0]
         raise ValueError("vector shape %s does not match level %d layout %s" % (tuple(t.shape), level, full))
 
+    def _same(self, t, ref, name):
+        """t must match ref (shape, dtype, device) and be contiguous: the
+        library reads and writes it with ref's layout."""
+        if (t is None or tuple(t.shape) != tuple(ref.shape) or t.dtype != ref.dtype or t.device != ref.device
+                or not t.is_contiguous()):
+            raise ValueError("%s must be a contiguous %s tensor of shape %s on %s"
+                             % (name, ref.dtype, tuple(ref.shape), ref.device))
+        return t
+
     @staticmethod
     def _flags(shifted, adjoint):
         return (L.ELH_SHIFTED if shifted else 0) | (L.ELH_ADJOINT if adjoint else 0)
@@ -123,20 +132,23 @@ class Problem:
     # -- level operations -----------------------------------------------------
     def apply(self, x, level=0, shifted=False, adjoint=False, out=None):
         nrhs = self._vec(x, level)
-        y = torch.empty_like(x) if out is None else out
+        y = torch.empty_like(x) if out is None else self._same(out, x, "out")
         L.check(self.lib.elh_apply(self.handle, level, self._flags(shifted, adjoint), _dtype_code(x), nrhs,
                                    _ptr(x), _ptr(y)))
         return y
 
-    def residual(self, b, x, level=0, shifted=False, adjoint=False):
+    def residual(self, b, x, level=0, shifted=False, adjoint=False, out=None):
         nrhs = self._vec(x, level)
-        r = torch.empty_like(x)
+        self._same(b, x, "b")
+        r = torch.empty_like(x) if out is None else self._same(out, x, "out")
         L.check(self.lib.elh_residual(self.handle, level, self._flags(shifted, adjoint), _dtype_code(x), nrhs,
                                       _ptr(b), _ptr(x), _ptr(r)))
         return r
 
     def restrict_residual(self, b, x=None, level=0, adjoint=False):
         nrhs = self._vec(b, level)
+        if x is not None:
+            self._same(x, b, "x")
         cshape, _ = self.level_shape(level + 1)
         full = (self.dim + 1,) + cshape
         out = torch.empty(((nrhs,) if b.dim() == len(full) + 1 else ()) + full, dtype=b.dtype, device=b.device)
@@ -146,11 +158,14 @@ class Problem:
 
     def prolong_add(self, e, x, level=0):
         nrhs = self._vec(x, level)
+        if self._vec(e, level + 1) != nrhs or e.dtype != x.dtype:
+            raise ValueError("e must hold %s vectors on level %d for every right-hand side" % (x.dtype, level + 1))
         L.check(self.lib.elh_prolong_add(self.handle, level, _dtype_code(x), nrhs, _ptr(e), _ptr(x)))
         return x
 
     def relax(self, b, x, colour, level=0, adjoint=False):
         nrhs = self._vec(x, level)
+        self._same(b, x, "b")
         L.check(self.lib.elh_relax(self.handle, level, self._flags(False, adjoint), _dtype_code(x), nrhs,
                                    colour, _ptr(b), _ptr(x)))
         return x

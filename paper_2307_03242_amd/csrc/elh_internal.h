@@ -48,7 +48,7 @@ template <typename TV, typename TW>
 int launch_multiaxpy(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
                      int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st);
 // w += sum_i coef_i V_i in place with ||w||^2 per rhs into out[2s] (part:
-// scratch of RED_BLOCKS*2 doubles per rhs); f (optional) receives w in TF.
+// scratch of 512*MAXDOT*2 doubles per rhs); f (optional) receives w in TF.
 template <typename TV, typename TF>
 int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
                      int64_t wstride_rhs, void* f, int64_t fstride_rhs, int64_t len, int nrhs, double* part,

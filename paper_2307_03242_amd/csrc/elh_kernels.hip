@@ -715,7 +715,10 @@ int launch_media_finish(int64_t n, const double* lam, const double* mu, const do
 // Krylov vector operations on batches of complex vectors (nrhs x len).
 // Reductions accumulate in float64, two stages, fixed order.
 // ---------------------------------------------------------------------------
-constexpr int RED_BLOCKS = 512;
+// The partial-sum scratch holds RED_PAIRS (block, entry) pairs per rhs
+// (512 * MAXDOT): a reduction over m entries may use up to RED_PAIRS / m
+// blocks, enough to keep every CU streaming on the large vectors.
+constexpr int RED_PAIRS = 512 * MAXDOT;
 constexpr int RED_THREADS = 256;
 
 template <typename TV, typename TW>
@@ -723,7 +726,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_multidot(int m, const TV* __res
                                                            int64_t vstride_rhs, const TW* __restrict__ w,
                                                            int64_t wstride_rhs, int64_t len,
                                                            double* __restrict__ part) {
-  // part[(s*RED_BLOCKS + block)*m*2 + 2i (+1)] = partial of <V_i, w>
+  // part[(s*gridDim.x + block)*m*2 + 2i (+1)] = partial of <V_i, w>
   const int s = blockIdx.y;
   double acc_re[MAXDOT], acc_im[MAXDOT];
 #pragma unroll
@@ -776,8 +779,9 @@ __global__ void __launch_bounds__(256) k_reduce_parts(int m2, int nblocks, const
 template <typename TV, typename TW>
 int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_rhs, const void* w,
                     int64_t wstride_rhs, int64_t len, int nrhs, double* part, double* out, hipStream_t st) {
+  if (m < 1 || m > MAXDOT) return (int)hipErrorInvalidValue;
   int nb = (int)((len + RED_THREADS - 1) / RED_THREADS);
-  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  if (nb > RED_PAIRS / m) nb = RED_PAIRS / m;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL((k_multidot<TV, TW>), dim3(nb, nrhs), dim3(RED_THREADS), 0, st, m, (const TV*)V, vstride_vec,
                      vstride_rhs, (const TW*)w, wstride_rhs, len, part);
@@ -888,7 +892,7 @@ int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_v
                      double* out, hipStream_t st) {
   if (m > MAXDOT) return (int)hipErrorInvalidValue;
   int nb = (int)((len + RED_THREADS - 1) / RED_THREADS);
-  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  if (nb > RED_PAIRS) nb = RED_PAIRS;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL((k_axpy_norm<TV, TF>), dim3(nb, nrhs), dim3(RED_THREADS), 0, st, m, coef, (const TV*)V,
                      vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part);

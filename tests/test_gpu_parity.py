@@ -271,6 +271,17 @@ def test_argument_errors_on_gpu():
     assert prob.lib.elh_apply(prob.handle, 0, 0, 2, 1, x.data_ptr(), x.data_ptr()) == -1
     with pytest.raises(ValueError):
         prob.apply(_dev(random_field((8, 8, 6), 1)))
+    # every extra vector must match x's layout before anything is launched
+    with pytest.raises(ValueError):
+        prob.apply(x, out=torch.empty(x.numel() // 2, dtype=x.dtype, device=x.device))
+    with pytest.raises(ValueError):
+        prob.residual(x.to(torch.complex64), x)
+    with pytest.raises(ValueError):
+        prob.residual(x, x, out=torch.empty_like(x)[..., :4].contiguous())
+    with pytest.raises(ValueError):
+        prob.relax(x[None].repeat(2, 1, 1, 1, 1).contiguous(), x, 0)
+    with pytest.raises(ValueError):
+        prob.prolong_add(x, x)  # e on the fine level instead of the coarse one
 
 
 @pytest.mark.parametrize("precond", [torch.complex128, torch.complex64])
