@@ -202,6 +202,24 @@ int elh_gradient(elh_handle* h, int nrhs, const void* u, const void* v,
 /* Number of levels, cells per axis (x-order) and spacing of `level`. */
 int elh_level_info(elh_handle* h, int level, int* n3, double* hl);
 
+/* Stencil autotuner (batching / set-up row of the hot path).  On its first
+ * use outside graph capture, each kind of 3D apply or residual (level,
+ * precision, residual or not, adjoint or not, nrhs) times its candidate
+ * x_3 chunks of the wavefront march (4, 8, 16, 32, 64 planes per workgroup,
+ * and the whole column when it has at most 64 planes) on the call's own
+ * buffers with HIP events on the handle's stream and keeps the fastest for
+ * the handle's lifetime.  The chunk never changes an output's arithmetic,
+ * so tuned and untuned results are bitwise equal.
+ * Environment: ELH_TUNE=0 (read at elh_create) keeps the default chunk
+ * heuristic; ELH_TUNE_CACHE=path loads earlier choices for the handle's
+ * grids at elh_create and appends new ones (one text line each).
+ * elh_stencil_choice reports the choice for one kind of call: *choice (host)
+ * = the chunk (> 0), or -1 when none has been made.  flags: ELH_ADJOINT selects the adjoint; residual: 0 or 1.
+ * Returns ELH_ERR_STATE / ELH_ERR_ARG on an invalid handle, level, dtype or
+ * NULL choice. */
+int elh_stencil_choice(elh_handle* h, int level, int dtype, int flags,
+                       int residual, int nrhs, int* choice);
+
 const char* elh_status_string(int status);
 const char* elh_last_error(void);
 

@@ -15,7 +15,7 @@ EXPORTED = [
     "elh_create", "elh_set_media", "elh_destroy", "elh_apply", "elh_residual",
     "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_coarse_solve",
     "elh_vcycle", "elh_solve", "elh_solve_adjoint", "elh_solve_batch", "elh_gradient",
-    "elh_level_info", "elh_status_string", "elh_last_error",
+    "elh_level_info", "elh_stencil_choice", "elh_status_string", "elh_last_error",
 ]
 
 
@@ -76,6 +76,7 @@ def load():
                             ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
         "elh_gradient": [H, ip, vp, vp, vp, vp, vp],
         "elh_level_info": [H, ip, ctypes.POINTER(ctypes.c_int), dp],
+        "elh_stencil_choice": [H, ip, ip, ip, ip, ip, ctypes.POINTER(ctypes.c_int)],
         "elh_status_string": [ip],
         "elh_last_error": [],
     }

@@ -103,6 +103,15 @@ class Problem:
         L.check(self.lib.elh_level_info(self.handle, level, n3, ctypes.byref(hl)))
         return tuple(reversed([n3[a] for a in range(self.dim)])), hl.value
 
+    def stencil_choice(self, level=0, dtype=torch.complex128, residual=False, adjoint=False, nrhs=1):
+        """x_3 chunk the stencil autotuner chose for one kind of 3D apply /
+        residual (> 0), -1 when none was made."""
+        c = ctypes.c_int()
+        L.check(self.lib.elh_stencil_choice(self.handle, level, L.ELH_C64 if dtype == torch.complex64 else L.ELH_C128,
+                                            self._flags(False, adjoint), 1 if residual else 0, nrhs,
+                                            ctypes.byref(c)))
+        return c.value
+
     def _vec(self, t, level):
         shp, _ = self.level_shape(level)
         if not t.is_cuda or t.device != self.device:

@@ -11,6 +11,8 @@
 
 #include <atomic>
 #include <complex>
+#include <map>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -114,6 +116,14 @@ struct elh_handle {
   int stencil = 0;          // ELH_STENCIL: 0 wavefront march (default), 1 LDS-tiled, 2 point-wise
   int zchunk = 32;          // x_3 planes per workgroup of the tiled stencil (ELH_ZCHUNK)
   int tile_y = 10;          // tile height (slots) of the float32 tiled stencil (ELH_TILE_Y: 6 or 10)
+  // stencil autotuner: chosen x_3 chunk of the wavefront march per (level,
+  // precision, input precision, residual, adjoint, nrhs); ELH_TUNE=0 keeps
+  // the default heuristic,
+  // ELH_TUNE_CACHE=path persists the choices across processes
+  int tune = 1;
+  std::map<int, int> tuned;
+  hipEvent_t tev[2] = {nullptr, nullptr};
+  std::string tune_path;
   int ok = 0;
 };
 
@@ -202,6 +212,9 @@ static int build_hierarchy(elh_handle* H, const double* lam, const double* mu, c
 static constexpr int64_t DENSE_MAX = 8192;
 static int build_dense(elh_handle* H);
 
+static void tune_load(elh_handle* H);
+static int tune_key(int l, int prec, int iprec, bool resid, bool adj, int nrhs);
+
 extern "C" int elh_create(const elh_desc* desc, const double* lam, const double* mu, const double* rho,
                           void* stream, elh_handle** out) {
   if (!out) return fail(ELH_ERR_ARG, "out is NULL");
@@ -221,6 +234,10 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
     if (ty && (atoi(ty) == 6 || atoi(ty) == 10)) H->tile_y = atoi(ty);
     const char* g = getenv("ELH_GRAPHS");
     if (g && strcmp(g, "0") == 0) H->use_graphs = 0;
+    const char* tu = getenv("ELH_TUNE");
+    if (tu && strcmp(tu, "0") == 0) H->tune = 0;
+    const char* tc = getenv("ELH_TUNE_CACHE");
+    if (tc && *tc) H->tune_path = tc;
   }
   H->st = (hipStream_t)stream;
   H->nlev = desc->levels;
@@ -279,6 +296,7 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
     elh_destroy(H);
     return rc;
   }
+  tune_load(H);
   H->ok = 1;
   *out = H;
   return 0;
@@ -312,9 +330,23 @@ extern "C" int elh_destroy(elh_handle* H) {
   for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
   H->graphs.clear();
   if (H->cap) (void)hipStreamDestroy(H->cap);
+  for (auto& e : H->tev)
+    if (e) (void)hipEventDestroy(e);
   if (H->hdots) (void)hipHostFree(H->hdots);
   if (H->hcoef) (void)hipHostFree(H->hcoef);
   delete H;
+  return 0;
+}
+
+extern "C" int elh_stencil_choice(elh_handle* H, int level, int dtype, int flags, int residual, int nrhs,
+                                  int* choice) {
+  if (!H || !H->ok) return fail(ELH_ERR_STATE, "invalid handle");
+  if (level < 0 || level >= H->nlev) return fail(ELH_ERR_ARG, "level %d out of range", level);
+  if (dtype != ELH_C64 && dtype != ELH_C128) return fail(ELH_ERR_ARG, "dtype must be ELH_C64 or ELH_C128");
+  if (!choice || nrhs < 1) return fail(ELH_ERR_ARG, "choice must be non-NULL and nrhs >= 1");
+  const int prec = prec_of(dtype);
+  auto it = H->tuned.find(tune_key(level, prec, prec, residual != 0, (flags & ELH_ADJOINT) != 0, nrhs));
+  *choice = it == H->tuned.end() ? -1 : it->second;
   return 0;
 }
 
@@ -346,19 +378,127 @@ static int ensure_cycle_bufs(elh_handle* H, int prec, int nrhs) {
 // ---------------------------------------------------------------------------
 // level operations (precision T)
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// stencil autotuner
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_file_mu;
+
+static int tune_key(int l, int prec, int iprec, bool resid, bool adj, int nrhs) {
+  return (((((l * 2 + prec) * 2 + iprec) * 2 + (resid ? 1 : 0)) * 2 + (adj ? 1 : 0)) << 8) | (nrhs & 0xff);
+}
+
+// choices persisted by earlier processes for this handle's grids
+static void tune_load(elh_handle* H) {
+  if (H->tune_path.empty()) return;
+  std::lock_guard<std::mutex> lk(g_tune_file_mu);
+  FILE* f = fopen(H->tune_path.c_str(), "r");
+  if (!f) return;
+  int n1, n2, n3, prec, iprec, resid, adj, nrhs, choice;
+  while (fscanf(f, "%d %d %d %d %d %d %d %d %d", &n1, &n2, &n3, &prec, &iprec, &resid, &adj, &nrhs, &choice) == 9) {
+    for (int l = 0; l < H->nlev; ++l)
+      if (H->lv[l].n[0] == n1 && H->lv[l].n[1] == n2 && H->lv[l].n[2] == n3)
+        H->tuned[tune_key(l, prec, iprec, resid != 0, adj != 0, nrhs)] = choice;
+  }
+  fclose(f);
+}
+
+static void tune_store(elh_handle* H, int l, int prec, int iprec, bool resid, bool adj, int nrhs, int choice) {
+  if (H->tune_path.empty()) return;
+  std::lock_guard<std::mutex> lk(g_tune_file_mu);
+  FILE* f = fopen(H->tune_path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "%d %d %d %d %d %d %d %d %d\n", H->lv[l].n[0], H->lv[l].n[1], H->lv[l].n[2], prec, iprec,
+          resid ? 1 : 0, adj ? 1 : 0, nrhs, choice);
+  fclose(f);
+}
+
+// One 3D apply / residual with input precision TI (float or T): x_3 chunk
+// `choice` (> 0) of the wavefront march (0: the point-wise kernel).
+template <typename T, typename TI>
+static int launch_choice(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y,
+                         int nrhs, int choice) {
+  const LevelArgs<T> a = largs<T>(H, l, shifted);
+  if (adj && sizeof(TI) != sizeof(T)) return (int)hipErrorInvalidValue;  // adjoint reads T input only
+  if (choice > 0) {
+    if (adj) return launch_apply3d_w3_adj<T>(a, x, b, y, nrhs, -choice, H->st);
+    return launch_apply3d_w3<T, TI>(a, x, b, y, nrhs, -choice, H->st);
+  }
+  if (sizeof(TI) != sizeof(T)) return (int)hipErrorInvalidValue;  // point-wise needs T input
+  return launch_apply<T>(a, H->d.dim, adj, x, b, y, nrhs, H->st);
+}
+
+// x_3 chunk for this call: the tuned choice if there is one; else,
+// when tuning is allowed here, time the candidates on the call's own
+// buffers (the operation is idempotent when y aliases neither x nor b) with
+// HIP events on the library's stream and keep the fastest.  The chunk only
+// changes which workgroup marches which planes, not any output's
+// arithmetic, so every choice gives bitwise the same result.  Never tunes
+// while the stream is being captured into a graph.
+template <typename T, typename TI>
+static int stencil_choice(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y,
+                          int nrhs) {
+  const int prec = sizeof(T) == 8 ? 0 : 1, iprec = sizeof(TI) == 8 ? 0 : 1;
+  const int key = tune_key(l, prec, iprec, b != nullptr, adj, nrhs);
+  auto it = H->tuned.find(key);
+  if (it != H->tuned.end()) return it->second;
+  const int dflt = 0x7fffffff;  // the launcher's heuristic
+  if (!H->tune || nrhs > 255 || y == x || y == b) return dflt;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(H->st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return dflt;
+  if (!H->tev[0]) {
+    if (hipEventCreate(&H->tev[0]) != hipSuccess || hipEventCreate(&H->tev[1]) != hipSuccess) return dflt;
+  }
+  const LevelData& L = H->lv[l];
+  std::vector<int> cand;
+  for (int zc : {4, 8, 16, 32, 64})
+    if (zc < L.n[2]) cand.push_back(zc);
+  if (L.n[2] <= 64) cand.push_back(L.n[2]);  // the whole column in one chunk
+  int best = dflt;
+  float tbest = 0;
+  for (int c : cand) {
+    if (launch_choice<T, TI>(H, l, shifted, adj, x, b, y, nrhs, c)) return dflt;  // warm-up
+    if (hipEventRecord(H->tev[0], H->st) != hipSuccess) return dflt;
+    for (int r = 0; r < 3; ++r)
+      if (launch_choice<T, TI>(H, l, shifted, adj, x, b, y, nrhs, c)) return dflt;
+    if (hipEventRecord(H->tev[1], H->st) != hipSuccess) return dflt;
+    float ms = 0;
+    if (hipEventSynchronize(H->tev[1]) != hipSuccess || hipEventElapsedTime(&ms, H->tev[0], H->tev[1]) != hipSuccess)
+      return dflt;
+    if (best == dflt || ms < tbest) {
+      best = c;
+      tbest = ms;
+    }
+  }
+  H->tuned[key] = best;
+  tune_store(H, l, prec, iprec, b != nullptr, adj, nrhs, best);
+  return best;
+}
+
+// 3D levels from 16^3 whose fields fit 32-bit byte offsets take the
+// wavefront march (x_3 chunk from the autotuner); 2D and smaller levels the
+// point-wise kernel.
 template <typename T>
 static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs) {
-  // the marching kernels pay off once a level has enough x_3 columns to fill
-  // the chip; small coarse levels use one thread per cell
-  // (the wavefront march addresses a field with 32-bit byte offsets)
   const bool fits32 = H->lv[l].fs * (int64_t)sizeof(cx<T>) <= (int64_t)0x7fffffff;
   if (H->d.dim == 3 && H->stencil == 0 && fits32 && H->lv[l].fs >= 16 * 16 * 16) {
-    if (adj) return launch_apply3d_w3_adj<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
-    return launch_apply3d_w3<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
+    const int c = stencil_choice<T, T>(H, l, shifted, adj, x, b, y, nrhs);
+    if (c == 0x7fffffff) {
+      if (adj) return launch_apply3d_w3_adj<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
+      return launch_apply3d_w3<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
+    }
+    return launch_choice<T, T>(H, l, shifted, adj, x, b, y, nrhs, c);
   }
   if (H->d.dim == 3 && !adj && H->stencil == 1 && H->lv[l].fs >= 24 * 24 * 24)
     return launch_apply3d_tiled<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->tile_y, H->st);
   return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);
+}
+
+// outer operator on float32 input (level 0, float64 arithmetic and output)
+static int op_apply_f32in(elh_handle* H, bool adj, const void* x, void* y, int nrhs) {
+  const int c = stencil_choice<double, float>(H, 0, false, adj, x, nullptr, y, nrhs);
+  if (c == 0x7fffffff || c == 0)
+    return launch_apply3d_w3<double, float>(largs<double>(H, 0, false), x, nullptr, y, nrhs, H->zchunk, H->st);
+  return launch_choice<double, float>(H, 0, false, adj, x, nullptr, y, nrhs, c);
 }
 
 static double level_damping(const elh_handle* H, int l) {
@@ -956,8 +1096,7 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
                         L0.fs * 16 <= (int64_t)0x7fffffff;
     if (!direct && ensure(ws.t, (size_t)nrhs * len * 16)) return ELH_ERR_OOM;
     auto AZ = [&](const void* zi, void* wo) {
-      if (direct) return launch_apply3d_w3<double, float>(largs<double>(H, 0, false), zi, nullptr, wo, nrhs,
-                                                         H->zchunk, H->st);
+      if (direct) return op_apply_f32in(H, adj, zi, wo, nrhs);
       CHK((launch_scale_copy<cx<float>, cx<double>>(nullptr, zi, len, ws.t.p, len, len, nrhs, H->st)));
       return op_apply<double>(H, 0, false, adj, ws.t.p, nullptr, wo, nrhs);
     };

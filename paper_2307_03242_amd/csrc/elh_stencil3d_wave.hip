@@ -662,9 +662,12 @@ k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restri
   else w3_march<2, T, TI, RESID>(C, DV);
 }
 
-// x_3 chunk length: at least ~8192 workgroups in flight on small grids
+// x_3 chunk length: zc < 0 asks for exactly -zc planes (the autotuner's
+// candidates); otherwise zc (default 32) shortened so that at least ~8192
+// workgroups are in flight on small grids
 static int w3_chunk(const int* n, int tiles_x, int nrhs, int zc) {
-  if (zc <= 0) zc = 32;
+  if (zc < 0) return -zc < n[2] ? -zc : n[2];
+  if (zc == 0) zc = 32;
   const int64_t cols = (int64_t)tiles_x * n[1] * nrhs;
   const int64_t want = (int64_t)n[2] * cols / 8192;
   if (want < zc) zc = (int)(want < 4 ? 4 : want);

@@ -1,0 +1,66 @@
+"""Stencil autotuner: choices are made once per kind of call, come from the
+candidate set, persist through ELH_TUNE_CACHE, and never change a result
+(the x_3 chunk only decides which workgroup marches which planes)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from synthetic import make_media, random_field, omega_for_ppw
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (10, 12, 70)  # (n_3, n_2, n_1): 8400 cells, two x_1 segments
+
+
+def _problem(env):
+    from paper_2307_03242_amd import Problem
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        m = make_media(SHAPE, 7)
+        return Problem(torch.from_numpy(m["lam"]), torch.from_numpy(m["mu"]), torch.from_numpy(m["rho"]),
+                       h=1.0, omega=omega_for_ppw(m["vs"].min(), 1.0, 10), gamma=0.01, alpha=0.3,
+                       abl_width=3.0, abl_amp=2.0, levels=1)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def test_tuned_choice_is_a_candidate_and_bitwise_neutral():
+    x = torch.from_numpy(random_field(SHAPE, 3, nrhs=2)).cuda()
+    b = torch.from_numpy(random_field(SHAPE, 4, nrhs=2)).cuda()
+    tuned = _problem({"ELH_TUNE": "1"})
+    fixed = _problem({"ELH_TUNE": "0"})
+    for dt in (torch.complex128, torch.complex64):
+        for adj in (False, True):
+            assert tuned.stencil_choice(0, dt, residual=False, adjoint=adj, nrhs=2) == -1
+            y1 = tuned.apply(x.to(dt), adjoint=adj)
+            y2 = fixed.apply(x.to(dt), adjoint=adj)
+            r1 = tuned.residual(b.to(dt), x.to(dt), shifted=True, adjoint=adj)
+            r2 = fixed.residual(b.to(dt), x.to(dt), shifted=True, adjoint=adj)
+            torch.cuda.synchronize()
+            assert torch.equal(y1, y2) and torch.equal(r1, r2)
+            for resid in (False, True):
+                c = tuned.stencil_choice(0, dt, residual=resid, adjoint=adj, nrhs=2)
+                assert c in (4, 8, SHAPE[0])
+                assert fixed.stencil_choice(0, dt, residual=resid, adjoint=adj, nrhs=2) == -1
+
+
+def test_tune_cache_persists_choices(tmp_path):
+    path = str(tmp_path / "elh_tune.txt")
+    x = torch.from_numpy(random_field(SHAPE, 5)).cuda()
+    a = _problem({"ELH_TUNE": "1", "ELH_TUNE_CACHE": path})
+    a.apply(x)
+    torch.cuda.synchronize()
+    c = a.stencil_choice(0, torch.complex128)
+    assert c > 0
+    lines = open(path).read().split("\n")
+    assert any(l.split()[:3] == [str(SHAPE[2]), str(SHAPE[1]), str(SHAPE[0])] for l in lines if l)
+    b = _problem({"ELH_TUNE": "1", "ELH_TUNE_CACHE": path})
+    assert b.stencil_choice(0, torch.complex128) == c  # loaded at creation, before any call
+    assert np.array_equal(b.apply(x).cpu().numpy(), a.apply(x).cpu().numpy())
