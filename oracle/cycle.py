@@ -9,7 +9,11 @@ Test infrastructure (see the package header).
   of lam, mu, rho; the absorbing layer keeps its physical width.
 * Cycle: Algorithm 1 (two-grid cycle) applied recursively with one
   recursive call (V-cycle) or two (W-cycle: the second call solves for the
-  residual left by the first, Section 2.2), nu1 pre- and nu2
+  residual left by the first, Section 2.2), or two calls used as the
+  preconditioners of two steps of a Krylov method on the coarse system
+  (K-cycle, Section 2.2; reading: flexible GCR, i.e. the coarse correction
+  minimises the coarse residual over the span of the two preconditioned
+  directions), nu1 pre- and nu2
   post-relaxations with
   red-black full Vanka, per-level damping w_l (Section 5.2 uses 0.55 /
   0.35 / 0.25 for finest/second/third levels).  The cycle preconditions
@@ -58,6 +62,7 @@ class CycleParams:
                  nu1=1, nu2=1, coarse="direct", coarse_sweeps=2,
                  coarse_restart=5, coarse_maxit=10, coarse_rtol=0.0,
                  coarse_damping=None, calls=1):
+        # calls: 1 V-cycle, 2 W-cycle, 3 K-cycle (two Krylov-accelerated calls)
         self.levels = levels
         self.calls = calls
         self.alpha = alpha
@@ -142,10 +147,33 @@ class Hierarchy:
         e = self.vcycle(rc, l + 1)
         if self.p.calls == 2 and l + 1 < len(self.levels) - 1:
             e = e + self.vcycle(rc - self.A[l + 1] @ e, l + 1)
+        elif self.p.calls == 3:
+            e = self.krylov_correction(rc, e, l + 1)
         x = x + self.P[l] @ e
         for _ in range(self.p.nu2):
             x = sm.sweep_rb(x, b, w)
         return x
+
+    def krylov_correction(self, rc, e1, l):
+        """K-cycle coarse correction on level l: two steps of flexible GCR on
+        A_l e = rc with the level-l cycle as preconditioner, e1 the first
+        preconditioned direction.  Step 1: v1 = A e1, a1 = <v1, rc>/<v1, v1>,
+        r1 = rc - a1 v1.  Step 2: e2 = cycle(r1), v2 = A e2 made orthogonal
+        to v1 (b = <v1, v2>/<v1, v1>), a2 = <v2, r1>/<v2, v2>.  The result
+        a1 e1 + a2 (e2 - b e1) minimises ||rc - A e|| over span{e1, e2}."""
+        A = self.A[l]
+        v1 = A @ e1
+        d11 = np.vdot(v1, v1)
+        a1 = np.vdot(v1, rc) / d11 if d11 != 0 else 0.0
+        r1 = rc - a1 * v1
+        e2 = self.vcycle(r1, l)
+        v2 = A @ e2
+        b = np.vdot(v1, v2) / d11 if d11 != 0 else 0.0
+        v2 = v2 - b * v1
+        e2 = e2 - b * e1
+        d22 = np.vdot(v2, v2)
+        a2 = np.vdot(v2, r1) / d22 if d22 != 0 else 0.0
+        return a1 * e1 + a2 * e2
 
     def vcycle_storage(self, b):
         lv = self.levels[0]

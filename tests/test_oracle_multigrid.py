@@ -242,6 +242,58 @@ def test_two_grid_is_linear_and_reduces_error():
     assert np.linalg.norm(e) < 0.5 ** 8 * n0
 
 
+def test_kcycle_with_exact_coarse_solve_is_the_two_grid_cycle():
+    """K-cycle pin 1: with an exact coarse solve the first preconditioned
+    direction already solves the coarse system, so the second Krylov step
+    adds nothing and the K-cycle equals the two-grid (V) cycle."""
+    shape = (16, 16)
+    m = make_media(shape, 3)
+    lv = _level(shape, omega=omega_for_ppw(m["vs"].min(), 1.0, 10), media=m, abl=(4.0, 2.0))
+    b = G.pack(lv, random_field(shape, 5))
+    hv = C.Hierarchy(lv, C.CycleParams(levels=2, alpha=0.3, coarse="direct", calls=1))
+    hk = C.Hierarchy(lv, C.CycleParams(levels=2, alpha=0.3, coarse="direct", calls=3))
+    xv, xk = hv.vcycle(b), hk.vcycle(b)
+    assert np.linalg.norm(xk - xv) <= 1e-12 * np.linalg.norm(xv)
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (8, 8, 8)])
+def test_kcycle_step_is_two_step_gmres_for_identity_preconditioner(shape):
+    """K-cycle pin 2: with the identity as the coarse preconditioner the two
+    directions span the Krylov space {r, A r}, so the K-cycle correction is
+    the two-step minimal-residual (GMRES(2)) solution from zero, here
+    computed independently as a least-squares problem over [r, A r]."""
+    m = make_media(shape, 4)
+    lv = _level(shape, omega=omega_for_ppw(m["vs"].min(), 1.0, 10), media=m)
+    hier = C.Hierarchy(lv, C.CycleParams(levels=2, alpha=0.3, coarse="relax", calls=3))
+    l = 1
+    A = hier.A[l]
+    rc = G.pack(hier.levels[l], random_field(tuple(reversed(hier.levels[l].n)), 6))
+    hier.vcycle = lambda b, lev=0: b.copy()  # identity preconditioner on every level
+    e = hier.krylov_correction(rc, rc.copy(), l)
+    K = np.stack([rc, A @ rc], axis=1)
+    c, *_ = np.linalg.lstsq(A @ K, rc, rcond=None)
+    ref = K @ c
+    assert np.linalg.norm(e - ref) <= 1e-10 * np.linalg.norm(ref)
+    # and the residual is orthogonal to A times both directions
+    res = rc - A @ e
+    assert abs(np.vdot(A @ K[:, 0], res)) <= 1e-10 * np.linalg.norm(rc) * np.linalg.norm(A @ K[:, 0])
+    assert abs(np.vdot(A @ K[:, 1], res)) <= 1e-10 * np.linalg.norm(rc) * np.linalg.norm(A @ K[:, 1])
+
+
+def test_kcycle_preconditioned_solve_matches_direct():
+    """the K-cycle as FGMRES preconditioner (3 levels, inexact coarse
+    solve) converges to the direct solution"""
+    shape = (32, 32)
+    m = make_media(shape, 5)
+    lv = _level(shape, omega=omega_for_ppw(m["vs"].min(), 1.0, 10), media=m, abl=(4.0, 2.0))
+    q = point_source(shape)
+    p = C.CycleParams(levels=3, alpha=0.3, coarse="krylov", coarse_sweeps=2, coarse_maxit=4, calls=3)
+    x, info = C.solve(lv, q, p, tol=1e-10, maxit=300)
+    xd = spla.spsolve(O.assemble(lv).tocsc(), G.pack(lv, q))
+    assert info["converged"]
+    assert np.linalg.norm(G.pack(lv, x) - xd) <= 1e-7 * np.linalg.norm(xd)
+
+
 # ----------------------------------------------------------------------------
 # adjoint and gradient (P13)
 # ----------------------------------------------------------------------------
