@@ -84,8 +84,10 @@ typedef struct {
                            delta_k = distance into the layer along x_k        */
   int levels;           /* multigrid levels, 1..8 (1 = coarsest solve only)   */
   int nu1, nu2;         /* pre/post red-black Vanka sweeps (Section 3.2)      */
-  int cycle_calls;      /* recursive calls per level: 1 = V-cycle, 2 = W-cycle
-                           (Section 2.2, below Algorithm 1)                   */
+  int cycle_calls;      /* recursive calls per level: 1 = V-cycle, 2 = W-cycle,
+                           3 = K-cycle: the two calls precondition two steps
+                           of flexible GCR on the coarse system (Section 2.2,
+                           below Algorithm 1)                                 */
   double damping[8];    /* Vanka damping w per level (Section 5.2)            */
   int coarse_mode;      /* ELH_COARSE_*                                       */
   int coarse_sweeps;    /* Vanka sweeps per coarse relaxation/preconditioning */
@@ -162,10 +164,11 @@ int elh_relax(elh_handle* h, int level, int flags, int dtype, int nrhs,
 int elh_coarse_solve(elh_handle* h, int flags, int dtype, int nrhs,
                      const void* b, void* x);
 
-/* x = V(nu1,nu2)-cycle (cycle_calls = 1) or W-cycle (cycle_calls = 2)
+/* x = V(nu1,nu2)-cycle (cycle_calls = 1), W-cycle (2) or K-cycle (3)
  * approximation of H_s^{-1} b on level 0 from a zero initial guess
- * (Algorithm 1 applied recursively).  flags:
- * ELH_ADJOINT for the cycle on H_s^H. */
+ * (Algorithm 1 applied recursively).  In the K-cycle the coarse correction
+ * of every level minimises the coarse residual over the span of the two
+ * preconditioned directions.  flags: ELH_ADJOINT for the cycle on H_s^H. */
 int elh_vcycle(elh_handle* h, int flags, int dtype, int nrhs, const void* b,
                void* x);
 

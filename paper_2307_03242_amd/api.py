@@ -30,7 +30,8 @@ class Problem:
 
     lam, mu, rho: float64 tensors of numpy shape (n_d, ..., n_1), any
     device (copied to the current GPU).  Lengths (h, abl_width) are in
-    physical units.
+    physical units.  cycle: 'V', 'W' or 'K' (the two coarse calls of every
+    level precondition two flexible-GCR steps on the coarse system).
     """
 
     def __init__(self, lam, mu, rho, h=1.0, omega=1.0, gamma=0.01, alpha=0.3,
@@ -58,7 +59,7 @@ class Problem:
         d.h, d.omega, d.gamma, d.alpha, d.beta = h, omega, gamma, alpha, beta
         d.abl_width, d.abl_amp = abl_width, abl_amp
         d.levels, d.nu1, d.nu2 = levels, nu1, nu2
-        d.cycle_calls = {'V': 1, 'W': 2}[cycle]
+        d.cycle_calls = {'V': 1, 'W': 2, 'K': 3}[cycle]
         damping = list(damping)
         while len(damping) < 8:
             damping.append(damping[-1])

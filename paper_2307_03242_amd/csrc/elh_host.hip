@@ -83,6 +83,8 @@ struct LevelData {
   int64_t fs, vs;
   DevBuf lam, mu, rho, kap, mu32, rho32, kap32;
   DevBuf b[2], x[2], r[2];  // cycle work per precision (0: f64, 1: f32)
+  DevBuf kw[2];             // K-cycle work on this (coarse) level: E1, V1, R1, V2, E2
+  DevBuf kc;                // K-cycle dots / coefficients / state of the step into this level
 };
 
 // Krylov workspace for one (level, precision, Z precision) combination.
@@ -173,7 +175,8 @@ static int check_desc(const elh_desc* d) {
   if (!(d->h > 0)) return fail(ELH_ERR_ARG, "h must be positive");
   if (!(d->beta > 0 && d->beta <= 1)) return fail(ELH_ERR_ARG, "beta must be in (0,1]");
   if (d->nu1 < 0 || d->nu2 < 0) return fail(ELH_ERR_ARG, "nu1/nu2 must be >= 0");
-  if (d->cycle_calls != 1 && d->cycle_calls != 2) return fail(ELH_ERR_ARG, "cycle_calls must be 1 (V) or 2 (W)");
+  if (d->cycle_calls < 1 || d->cycle_calls > 3)
+    return fail(ELH_ERR_ARG, "cycle_calls must be 1 (V), 2 (W) or 3 (K)");
   if (d->coarse_mode < 0 || d->coarse_mode > 2) return fail(ELH_ERR_ARG, "bad coarse_mode");
   if (d->coarse_mode != ELH_COARSE_DENSE && d->coarse_sweeps < 1) return fail(ELH_ERR_ARG, "coarse_sweeps must be >= 1");
   if (d->coarse_mode == ELH_COARSE_KRYLOV && (d->coarse_restart < 1 || d->coarse_maxit < 1))
@@ -318,7 +321,8 @@ extern "C" int elh_destroy(elh_handle* H) {
     LevelData& L = H->lv[l];
     release(L.lam); release(L.mu); release(L.rho); release(L.kap);
     release(L.mu32); release(L.rho32); release(L.kap32);
-    for (int p = 0; p < 2; ++p) { release(L.b[p]); release(L.x[p]); release(L.r[p]); }
+    for (int p = 0; p < 2; ++p) { release(L.b[p]); release(L.x[p]); release(L.r[p]); release(L.kw[p]); }
+    release(L.kc);
   }
   for (int p = 0; p < 2; ++p) {
     KrylovWS* ws[2] = {&H->kout[p], &H->kin[p]};
@@ -371,6 +375,9 @@ static int ensure_cycle_bufs(elh_handle* H, int prec, int nrhs) {
     LevelData& L = H->lv[l];
     size_t bytes = (size_t)nrhs * L.vs * csz(prec);
     if (ensure(L.b[prec], bytes) || ensure(L.x[prec], bytes) || ensure(L.r[prec], bytes)) return ELH_ERR_OOM;
+    if (H->d.cycle_calls == 3 && l > 0) {
+      if (ensure(L.kw[prec], 5 * bytes) || ensure(L.kc, (size_t)MAXRHS_KRYLOV * 20 * 8)) return ELH_ERR_OOM;
+    }
   }
   return 0;
 }
@@ -883,8 +890,38 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
     CHK(op_apply<T>(H, l, true, adj, x, b, L.r[prec].p, nrhs));
     r = L.r[prec].p;
   }
-  CHK(launch_restrict<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, r, C.b[prec].p, nrhs, H->st));
-  CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
+  if (H->d.cycle_calls == 3) {
+    // K-cycle: the coarse correction from two steps of flexible GCR on the
+    // coarse system, each preconditioned by the coarse cycle (or the
+    // coarsest solve); workspace E1, V1, R1, V2, E2 on the coarse level
+    typedef cx<T> CT;
+    const int64_t vec = (int64_t)nrhs * C.vs;
+    CT* E1 = (CT*)C.kw[prec].p;
+    CT* V1 = E1 + vec;
+    CT* R1 = E1 + 2 * vec;
+    CT* V2 = E1 + 3 * vec;
+    CT* E2 = E1 + 4 * vec;
+    double* kd = (double*)C.kc.p;                     // dots: 6 doubles per rhs
+    double* kc1 = kd + 6 * MAXRHS_KRYLOV;             // stage-1 coefficients: 2 per rhs
+    double* kc2 = kc1 + 2 * MAXRHS_KRYLOV;            // stage-2 coefficients: 4 per rhs
+    double* ks = kc2 + 4 * MAXRHS_KRYLOV;             // state: 4 per rhs
+    CHK(launch_restrict<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, r, R1, nrhs, H->st));
+    CHK(cycle<T>(H, l + 1, adj, R1, E1, nrhs));
+    CHK(op_apply<T>(H, l + 1, true, adj, E1, nullptr, V1, nrhs));
+    CHK((launch_multidot<CT, CT>(2, V1, vec, C.vs, V1, C.vs, C.vs, nrhs, (double*)H->part.p, kd, H->st)));
+    CHK(launch_kcycle_coef(1, kd, kc1, ks, nrhs, H->st));
+    CHK((launch_multiaxpy<CT, CT>(1, kc1, V1, 0, C.vs, R1, C.vs, C.vs, nrhs, H->st)));
+    CHK(cycle<T>(H, l + 1, adj, R1, E2, nrhs));
+    CHK(op_apply<T>(H, l + 1, true, adj, E2, nullptr, V2, nrhs));
+    CHK((launch_multidot<CT, CT>(3, V1, vec, C.vs, V2, C.vs, C.vs, nrhs, (double*)H->part.p, kd, H->st)));
+    CHK(launch_kcycle_coef(2, kd, kc2, ks, nrhs, H->st));
+    CHK(launch_zero(C.x[prec].p, (int64_t)nrhs * C.vs * csz(prec), H->st));
+    CHK((launch_multiaxpy<CT, CT>(2, kc2, E1, 4 * vec, C.vs, C.x[prec].p, C.vs, C.vs, nrhs, H->st)));
+  } else {
+    CHK(launch_restrict<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, r, C.b[prec].p, nrhs,
+                           H->st));
+    CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
+  }
   if (H->d.cycle_calls == 2 && l + 1 < H->nlev - 1) {
     // W-cycle: second coarse cycle on the coarse residual, added to the first
     CHK(op_apply<T>(H, l + 1, true, adj, C.x[prec].p, C.b[prec].p, C.r[prec].p, nrhs));

@@ -53,6 +53,8 @@ template <typename TV, typename TF>
 int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
                      int64_t wstride_rhs, void* f, int64_t fstride_rhs, int64_t len, int nrhs, double* part,
                      double* out, hipStream_t st);
+// K-cycle step coefficients from the dots (stage 1: m = 2, stage 2: m = 3).
+int launch_kcycle_coef(int stage, const double* dots, double* coef, double* state, int nrhs, hipStream_t st);
 template <typename TX, typename TY>
 int launch_scale_copy(const double* a, const void* x, int64_t xstride, void* y, int64_t ystride, int64_t len,
                       int nrhs, hipStream_t st);

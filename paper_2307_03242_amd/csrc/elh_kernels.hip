@@ -909,6 +909,50 @@ template int launch_axpy_norm<cx<float>, cx<float>>(int, const double*, const vo
                                                     int64_t, void*, int64_t, int64_t, int, double*, double*,
                                                     hipStream_t);
 
+// K-cycle coefficients, one thread per rhs (dots from k_multidot: entry i
+// of rhs s at dots[(s*m + i)*2], complex).
+// stage 1: dots = <V1,V1>, <R1,V1>          (m = 2)
+//   a1 = conj(<R1,V1>) / <V1,V1>;  coef[s] = -a1 (for R1 += coef V1);
+//   state[s] = (a1, <V1,V1>).
+// stage 2: dots = <V1,V2>, <R1,V2>, <V2,V2> (m = 3), R1 now r1 = rc - a1 V1
+//   b = <V1,V2>/<V1,V1>,  n2 = <V2,V2> - |<V1,V2>|^2/<V1,V1>  (= |V2 - b V1|^2),
+//   a2 = conj(<R1,V2>)/n2  (<V2 - b V1, r1> = <V2, r1> since r1 is orthogonal to V1),
+//   coef[s] = (a1 - a2 b, a2)  for  e = coef0 E1 + coef1 E2.
+// Zero denominators give zero coefficients.
+__global__ void k_kcycle_coef(int stage, const double* __restrict__ dots, double* __restrict__ coef,
+                              double* __restrict__ state, int nrhs) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nrhs) return;
+  if (stage == 1) {
+    const double d11 = dots[(s * 2 + 0) * 2];
+    const double rr = dots[(s * 2 + 1) * 2], ri = dots[(s * 2 + 1) * 2 + 1];
+    const double a1r = d11 != 0.0 ? rr / d11 : 0.0, a1i = d11 != 0.0 ? -ri / d11 : 0.0;
+    coef[s * 2] = -a1r;
+    coef[s * 2 + 1] = -a1i;
+    state[s * 4] = a1r;
+    state[s * 4 + 1] = a1i;
+    state[s * 4 + 2] = d11;
+    state[s * 4 + 3] = 0.0;
+  } else {
+    const double a1r = state[s * 4], a1i = state[s * 4 + 1], d11 = state[s * 4 + 2];
+    const double pr = dots[(s * 3 + 0) * 2], pi = dots[(s * 3 + 0) * 2 + 1];   // <V1,V2>
+    const double qr = dots[(s * 3 + 1) * 2], qi = dots[(s * 3 + 1) * 2 + 1];   // <R1,V2>
+    const double d22 = dots[(s * 3 + 2) * 2];                                   // <V2,V2>
+    const double br = d11 != 0.0 ? pr / d11 : 0.0, bi = d11 != 0.0 ? pi / d11 : 0.0;
+    const double n2 = d11 != 0.0 ? d22 - (pr * pr + pi * pi) / d11 : d22;
+    const double a2r = n2 > 0.0 ? qr / n2 : 0.0, a2i = n2 > 0.0 ? -qi / n2 : 0.0;
+    coef[s * 4] = a1r - (a2r * br - a2i * bi);
+    coef[s * 4 + 1] = a1i - (a2r * bi + a2i * br);
+    coef[s * 4 + 2] = a2r;
+    coef[s * 4 + 3] = a2i;
+  }
+}
+
+int launch_kcycle_coef(int stage, const double* dots, double* coef, double* state, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_kcycle_coef, dim3((nrhs + 63) / 64), dim3(64), 0, st, stage, dots, coef, state, nrhs);
+  return (int)hipGetLastError();
+}
+
 // y[s] = a[s] * x[s]   (a complex double per rhs), with type conversion
 template <typename TX, typename TY>
 __global__ void __launch_bounds__(256) k_scale_copy(const double* __restrict__ a, const TX* __restrict__ x,
