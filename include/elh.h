@@ -111,6 +111,15 @@ typedef struct {        /* (host) one record per right-hand side              */
   int restarts;
   int status;           /* ELH_OK / ELH_NOT_CONVERGED / ELH_ERR_NUMERIC       */
   double relres;        /* final true relative residual, float64              */
+  double* history;      /* in: NULL, or a host array of history_cap doubles   */
+  int history_cap;      /*   that receives the FGMRES estimate of the         */
+  int history_len;      /*   relative residual after each iteration; out:     */
+                        /*   entries written (min(iters, history_cap))        */
+  double t_total_ms;    /* out: wall time of the call (same for every rhs)    */
+  double t_precond_ms;  /* out: GPU time in the preconditioner cycles         */
+  double t_apply_ms;    /* out: GPU time in the outer operator A z            */
+  double t_orth_ms;     /* out: Gram-Schmidt passes, reductions and their     */
+                        /*   host round trips                                 */
 } elh_solve_stats;
 
 typedef struct elh_handle elh_handle;

@@ -41,7 +41,10 @@ class SolveOpts(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("status", ctypes.c_int),
-                ("relres", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("history_cap", ctypes.c_int), ("history_len", ctypes.c_int),
+                ("t_total_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
+                ("t_apply_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double)]
 
 
 _lib = None

@@ -24,6 +24,15 @@ def _dtype_code(t):
     raise TypeError("vectors must be complex64 or complex128, got %s" % t.dtype)
 
 
+def _info(s):
+    """one solve-stats record as a dict (history: the per-iteration FGMRES
+    residual estimates; times in ms)"""
+    return dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres,
+                history=[s.history[i] for i in range(s.history_len)] if s.history else [],
+                t_total_ms=s.t_total_ms, t_precond_ms=s.t_precond_ms, t_apply_ms=s.t_apply_ms,
+                t_orth_ms=s.t_orth_ms)
+
+
 class Problem:
     """One elastic Helmholtz problem (media + discretisation + solver
     parameters) living on one GPU.
@@ -202,9 +211,12 @@ class Problem:
         u = torch.empty_like(q) if out is None else out
         opts = L.SolveOpts(restart, maxit, rtol)
         stats = (L.SolveStats * nrhs)()
+        hist = [(ctypes.c_double * maxit)() for _ in range(nrhs)]
+        for s, h in zip(stats, hist):
+            s.history = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
+            s.history_cap = maxit
         code = L.check(fn(self.handle, nrhs, _ptr(q), _ptr(u), ctypes.byref(opts), stats))
-        info = [dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres) for s in stats]
-        return u, info, code
+        return u, [_info(s) for s in stats], code
 
     def solve(self, q, restart=5, maxit=500, rtol=1e-6, out=None):
         """u = H^{-1} q by preconditioned FGMRES; returns (u, info, code)."""
@@ -234,11 +246,14 @@ class Problem:
         up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
         opts = L.SolveOpts(restart, maxit, rtol)
         stats = (L.SolveStats * sum(nr))()
+        hist = [(ctypes.c_double * maxit)() for _ in range(sum(nr))]
+        for s, h in zip(stats, hist):
+            s.history = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
+            s.history_cap = maxit
         code = L.check(lib.elh_solve_batch(n, hs, nrh, qp, up, ctypes.byref(opts), stats))
         infos, k = [], 0
         for r in nr:
-            infos.append([dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres)
-                          for s in stats[k:k + r]])
+            infos.append([_info(s) for s in stats[k:k + r]])
             k += r
         return us, infos, code
 

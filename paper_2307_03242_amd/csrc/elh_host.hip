@@ -10,6 +10,7 @@
 #include <string>
 
 #include <atomic>
+#include <chrono>
 #include <complex>
 #include <map>
 #include <mutex>
@@ -543,6 +544,34 @@ static int op_sweeps_from_zero(elh_handle* H, int l, bool adj, const void* b, vo
 struct GmresStats {
   std::vector<int> iters, restarts, status;
   std::vector<double> relres;
+  std::vector<std::vector<double>> history;  // per rhs: residual estimate after each iteration
+  bool timing = false;                        // record the time split below (events on the stream)
+  double t_precond = 0, t_apply = 0, t_orth = 0;  // ms
+};
+
+// GPU-time accounting of one solve: events recorded between the phases of
+// an iteration, read after the host synchronisation that follows them.
+struct PhaseTimer {
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool on = false;
+  explicit PhaseTimer(bool want) {
+    if (!want) return;
+    on = true;
+    for (auto& x : e)
+      if (hipEventCreate(&x) != hipSuccess) on = false;
+  }
+  ~PhaseTimer() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  void mark(int i, hipStream_t st) {
+    if (on && hipEventRecord(e[i], st) != hipSuccess) on = false;
+  }
+  double span(int a, int b) {
+    float ms = 0;
+    if (!on || hipEventElapsedTime(&ms, e[a], e[b]) != hipSuccess) return 0.0;
+    return ms;
+  }
 };
 
 // dots[s][i] for i < m, from the device buffer (synchronises)
@@ -618,6 +647,8 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
   st_out.restarts.assign(nrhs, 0);
   st_out.status.assign(nrhs, ELH_NOT_CONVERGED);
   st_out.relres.assign(nrhs, 1.0);
+  st_out.history.assign(nrhs, std::vector<double>());
+  PhaseTimer tm(st_out.timing);
   std::vector<char> active(nrhs);
   int nact = 0;
   for (int s = 0; s < nrhs; ++s) {
@@ -647,9 +678,12 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
     if (cast_in) CHK((launch_scale_copy<CT, CZ>(nullptr, V, len, cyc_in, len, len, nrhs, st)));
     int j;
     for (j = 0; j < m; ++j) {
+      tm.mark(0, st);
       CHK(M(cast_in ? (const void*)cyc_in : (const void*)(V + j * vstr), (void*)(Z + j * vstr)));
+      tm.mark(1, st);
       CT* W = V + (j + 1) * vstr;
       CHK(AZ((const void*)(Z + j * vstr), (void*)W));
+      tm.mark(2, st);
       ++iters;
       // classical Gram-Schmidt on the unnormalised basis
       CHK((launch_multidot<CT, CT>(j + 1, V, vstr, len, W, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p,
@@ -666,7 +700,11 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
       CHK((launch_axpy_norm<CT, CZ>(j + 1, (const double*)H->coef.p, V, vstr, len, W, len,
                                     cast_in ? cyc_in : nullptr, len, len, nrhs, (double*)H->part.p,
                                     (double*)H->dots.p, st)));
+      tm.mark(3, st);
       CHK(fetch_dots(H, nrhs, 1, dots));
+      st_out.t_precond += tm.span(0, 1);
+      st_out.t_apply += tm.span(1, 2);
+      st_out.t_orth += tm.span(2, 3);
       bool any_live = false;
       for (int s = 0; s < nrhs; ++s) {
         const double sj = sig[(size_t)s * (m + 1) + j];
@@ -710,6 +748,7 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
         gs[j] = c * gs[j];
         jend[s] = j;
         double res = std::abs(gs[j + 1]) / nb[s];
+        st_out.history[s].push_back(res);
         if (res <= rtol || hn == 0) live[s] = 0;
         if (live[s]) any_live = true;
       }
@@ -1108,6 +1147,8 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
   LevelData& L0 = H->lv[0];
   const int64_t len = L0.vs;
   GmresStats gs;
+  gs.timing = stats != nullptr;
+  const auto wall0 = std::chrono::steady_clock::now();
   auto AR = [&](const void* xi, const void* bi, void* ro) {
     return op_apply<double>(H, 0, false, adj, xi, bi, ro, nrhs);
   };
@@ -1141,6 +1182,8 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
                               L0.b[1].p);
   }
   if (rc < 0) return rc;
+  const double wall =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
   int worst = ELH_OK;
   for (int s = 0; s < nrhs; ++s) {
     if (stats) {
@@ -1148,6 +1191,14 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
       stats[s].restarts = gs.restarts[s];
       stats[s].status = gs.status[s];
       stats[s].relres = gs.relres[s];
+      const int nh = (int)gs.history[s].size();
+      const int cap = stats[s].history && stats[s].history_cap > 0 ? stats[s].history_cap : 0;
+      stats[s].history_len = nh < cap ? nh : cap;
+      for (int i = 0; i < stats[s].history_len; ++i) stats[s].history[i] = gs.history[s][i];
+      stats[s].t_total_ms = wall;
+      stats[s].t_precond_ms = gs.t_precond;
+      stats[s].t_apply_ms = gs.t_apply;
+      stats[s].t_orth_ms = gs.t_orth;
     }
     if (gs.status[s] != ELH_OK) worst = gs.status[s];
   }

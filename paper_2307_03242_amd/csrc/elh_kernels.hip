@@ -721,24 +721,29 @@ int launch_media_finish(int64_t n, const double* lam, const double* mu, const do
 constexpr int RED_PAIRS = 512 * MAXDOT;
 constexpr int RED_THREADS = 256;
 
-template <typename TV, typename TW>
+// MC > 0: exactly MC dots (accumulators and loop fixed at compile time);
+// MC = 0: m dots, m <= MAXDOT.
+template <typename TV, typename TW, int MC>
 __global__ void __launch_bounds__(RED_THREADS) k_multidot(int m, const TV* __restrict__ V, int64_t vstride_vec,
                                                            int64_t vstride_rhs, const TW* __restrict__ w,
                                                            int64_t wstride_rhs, int64_t len,
                                                            double* __restrict__ part) {
   // part[(s*gridDim.x + block)*m*2 + 2i (+1)] = partial of <V_i, w>
+  constexpr int NA = MC > 0 ? MC : MAXDOT;
+  if (MC > 0) m = MC;
   const int s = blockIdx.y;
-  double acc_re[MAXDOT], acc_im[MAXDOT];
+  double acc_re[NA], acc_im[NA];
 #pragma unroll
-  for (int i = 0; i < MAXDOT; ++i) { acc_re[i] = 0; acc_im[i] = 0; }
+  for (int i = 0; i < NA; ++i) { acc_re[i] = 0; acc_im[i] = 0; }
   const TW* ws = w + s * wstride_rhs;
+  const TV* vs = V + s * vstride_rhs;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
     auto wv = ws[t];
     double wr = (double)wv.re, wi = (double)wv.im;
 #pragma unroll
-    for (int i = 0; i < MAXDOT; ++i) {
-      if (i < m) {
-        auto vv = V[i * vstride_vec + s * vstride_rhs + t];
+    for (int i = 0; i < NA; ++i) {
+      if (MC > 0 || i < m) {
+        auto vv = vs[i * vstride_vec + t];
         double vr = (double)vv.re, vi = (double)vv.im;
         acc_re[i] += vr * wr + vi * wi;  // conj(v) * w
         acc_im[i] += vr * wi - vi * wr;
@@ -748,7 +753,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_multidot(int m, const TV* __res
   __shared__ double red[RED_THREADS];
   for (int i = 0; i < m; ++i) {
     for (int part_ri = 0; part_ri < 2; ++part_ri) {
-      red[threadIdx.x] = part_ri == 0 ? acc_re[i] : acc_im[i];
+      double v = 0;
+#pragma unroll
+      for (int k = 0; k < NA; ++k)
+        if (k == i) v = part_ri == 0 ? acc_re[k] : acc_im[k];
+      red[threadIdx.x] = v;
       __syncthreads();
       for (int o = RED_THREADS / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
@@ -783,8 +792,18 @@ int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_r
   int nb = (int)((len + RED_THREADS - 1) / RED_THREADS);
   if (nb > RED_PAIRS / m) nb = RED_PAIRS / m;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL((k_multidot<TV, TW>), dim3(nb, nrhs), dim3(RED_THREADS), 0, st, m, (const TV*)V, vstride_vec,
-                     vstride_rhs, (const TW*)w, wstride_rhs, len, part);
+  const dim3 grd(nb, nrhs), blk(RED_THREADS);
+  const TV* Vp = (const TV*)V;
+  const TW* wp = (const TW*)w;
+  switch (m) {
+    case 1: hipLaunchKernelGGL((k_multidot<TV, TW, 1>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 2: hipLaunchKernelGGL((k_multidot<TV, TW, 2>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 3: hipLaunchKernelGGL((k_multidot<TV, TW, 3>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 4: hipLaunchKernelGGL((k_multidot<TV, TW, 4>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 5: hipLaunchKernelGGL((k_multidot<TV, TW, 5>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 6: hipLaunchKernelGGL((k_multidot<TV, TW, 6>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    default: hipLaunchKernelGGL((k_multidot<TV, TW, 0>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part);
+  }
   hipLaunchKernelGGL(k_reduce_parts, dim3(2 * m, nrhs), dim3(256), 0, st, 2 * m, nb, part, out);
   return (int)hipGetLastError();
 }
@@ -834,17 +853,19 @@ template int launch_multiaxpy<cx<float>, cx<float>>(int, const double*, const vo
 // 2b+1, the second zero, so k_reduce_parts yields ||w||^2 as a complex
 // number), and when f is non-NULL the updated w is also written to f in
 // precision TF (the input of the next preconditioner application).
-template <typename TV, typename TF>
+template <typename TV, typename TF, int MC>
 __global__ void __launch_bounds__(RED_THREADS) k_axpy_norm(int m, const double* __restrict__ coef,
                                                             const TV* __restrict__ V, int64_t vstride_vec,
                                                             int64_t vstride_rhs, TV* __restrict__ w,
                                                             int64_t wstride_rhs, TF* __restrict__ f,
                                                             int64_t fstride_rhs, int64_t len,
                                                             double* __restrict__ part) {
+  constexpr int NA = MC > 0 ? MC : MAXDOT;
+  if (MC > 0) m = MC;
   const int s = blockIdx.y;
-  double cr[MAXDOT], ci[MAXDOT];
+  double cr[NA], ci[NA];
 #pragma unroll
-  for (int i = 0; i < MAXDOT; ++i) {
+  for (int i = 0; i < NA; ++i) {
     cr[i] = i < m ? coef[(s * m + i) * 2] : 0.0;
     ci[i] = i < m ? coef[(s * m + i) * 2 + 1] : 0.0;
   }
@@ -854,8 +875,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_axpy_norm(int m, const double* 
     auto wv = ws[t];
     double re = (double)wv.re, im = (double)wv.im;
 #pragma unroll
-    for (int i = 0; i < MAXDOT; ++i) {
-      if (i < m) {
+    for (int i = 0; i < NA; ++i) {
+      if (MC > 0 || i < m) {
         auto vv = V[i * vstride_vec + s * vstride_rhs + t];
         const double vr = (double)vv.re, vi = (double)vv.im;
         re += cr[i] * vr - ci[i] * vi;
@@ -894,8 +915,16 @@ int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_v
   int nb = (int)((len + RED_THREADS - 1) / RED_THREADS);
   if (nb > RED_PAIRS) nb = RED_PAIRS;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL((k_axpy_norm<TV, TF>), dim3(nb, nrhs), dim3(RED_THREADS), 0, st, m, coef, (const TV*)V,
-                     vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part);
+  const dim3 grd(nb, nrhs), blk(RED_THREADS);
+  const TV* Vp = (const TV*)V;
+  switch (m) {
+    case 1: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 1>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    case 2: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 2>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    case 3: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 3>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    case 4: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 4>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    case 5: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 5>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    default: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 0>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part);
+  }
   hipLaunchKernelGGL(k_reduce_parts, dim3(2, nrhs), dim3(256), 0, st, 2, nb, part, out);
   return (int)hipGetLastError();
 }

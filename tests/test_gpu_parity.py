@@ -282,6 +282,24 @@ def test_solve_mixed_precision_matches_f64():
     assert err <= 1e-5
 
 
+def test_solve_reports_history_and_time_split():
+    """solve stats: one FGMRES residual estimate per iteration (ending at
+    the tolerance), and a GPU time split that fits inside the wall time"""
+    shape = (16, 16, 16)
+    P = _params(shape, levels=3, coarse="krylov")
+    prob = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6, precond=torch.complex64, cycle="K")
+    q = np.stack([point_source(shape), random_field(shape, 41)])
+    u, info, code = prob.solve(_dev(q), restart=5, maxit=300, rtol=1e-6)
+    assert code == 0
+    for i in info:
+        h = i["history"]
+        assert len(h) == i["iters"] and h[-1] <= 1e-6 and all(v >= 0 for v in h)
+        assert h[-1] < h[0]
+        parts = i["t_precond_ms"] + i["t_apply_ms"] + i["t_orth_ms"]
+        assert i["t_precond_ms"] > 0 and i["t_apply_ms"] > 0 and i["t_orth_ms"] > 0
+        assert parts <= 1.05 * i["t_total_ms"]
+
+
 def test_solve_batched_rhs_independent():
     shape = (16, 16, 16)
     P = _params(shape, levels=3, coarse="relax")
