@@ -217,8 +217,8 @@ int elh_level_info(elh_handle* h, int level, int* n3, double* hl);
 /* Stencil autotuner (batching / set-up row of the hot path).  On its first
  * use outside graph capture, each kind of 3D apply or residual (level,
  * precision, residual or not, adjoint or not, nrhs) times its candidate
- * x_3 chunks of the wavefront march (4, 8, 16, 32, 64 planes per workgroup,
- * and the whole column when it has at most 64 planes) on the call's own
+ * x_3 chunks of the wavefront march (4, 8, 16, 32, 64 planes per workgroup;
+ * on columns of at most 64 planes also 1, 2 and the whole column) on the call's own
  * buffers with HIP events on the handle's stream and keeps the fastest for
  * the handle's lifetime.  The chunk never changes an output's arithmetic,
  * so tuned and untuned results are bitwise equal.

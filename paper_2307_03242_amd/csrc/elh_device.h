@@ -56,6 +56,8 @@ template <typename T> struct LevelArgs {
   const T* mu;       // cell media (fs each)
   const T* rho;
   const T* kap;      // 1/(lam+mu)
+  const T* ablz;     // 3D: absorbing-layer term along x_3, amp*(delta/width)^2, at the
+                     // cell centres (entries 0..n3-1) and at the lower faces (n3..2*n3-1)
 };
 
 template <int DIM> __device__ __forceinline__ bool in_grid(const int* n, const int* j) {

@@ -85,6 +85,7 @@ struct LevelData {
   DevBuf lam, mu, rho, kap, mu32, rho32, kap32;
   DevBuf b[2], x[2], r[2];  // cycle work per precision (0: f64, 1: f32)
   DevBuf kw[2];             // K-cycle work on this (coarse) level: E1, V1, R1, V2, E2
+  DevBuf ablz[2];           // absorbing-layer term along x_3 per plane (centres, faces), f64 / f32
   DevBuf kc;                // K-cycle dots / coefficients / state of the step into this level
 };
 
@@ -154,10 +155,12 @@ static LevelArgs<T> largs(const elh_handle* H, int l, bool shifted) {
     a.mu = (const T*)L.mu.p;
     a.rho = (const T*)L.rho.p;
     a.kap = (const T*)L.kap.p;
+    a.ablz = (const T*)L.ablz[0].p;
   } else {
     a.mu = (const T*)L.mu32.p;
     a.rho = (const T*)L.rho32.p;
     a.kap = (const T*)L.kap32.p;
+    a.ablz = (const T*)L.ablz[1].p;
   }
   return a;
 }
@@ -232,8 +235,8 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
     const char* e = getenv("ELH_STENCIL");
     if (e && strcmp(e, "tiled") == 0) H->stencil = 1;
     if (e && strcmp(e, "generic") == 0) H->stencil = 2;
-    const char* z = getenv("ELH_ZCHUNK");
-    if (z && atoi(z) > 0) H->zchunk = atoi(z);
+    const char* z = getenv("ELH_ZCHUNK");  // > 0: default chunk (shortened on small grids); < 0: exactly -z
+    if (z && atoi(z) != 0) H->zchunk = atoi(z);
     const char* ty = getenv("ELH_TILE_Y");
     if (ty && (atoi(ty) == 6 || atoi(ty) == 10)) H->tile_y = atoi(ty);
     const char* g = getenv("ELH_GRAPHS");
@@ -259,6 +262,28 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
     e |= ensure(L.mu32, L.fs * 4);
     e |= ensure(L.rho32, L.fs * 4);
     e |= ensure(L.kap32, L.fs * 4);
+    e |= ensure(L.ablz[0], (size_t)2 * L.n[2] * 8);
+    e |= ensure(L.ablz[1], (size_t)2 * L.n[2] * 4);
+    if (!e) {
+      // amp * (delta/width)^2 along x_3 at plane centres (t + 1/2) h and
+      // lower faces t h, delta the distance into the layer (physical width)
+      std::vector<double> t64(2 * L.n[2]);
+      std::vector<float> t32(2 * L.n[2]);
+      const double w = desc->abl_width, len = L.n[2] * L.h;
+      for (int t = 0; t < L.n[2]; ++t)
+        for (int f = 0; f < 2; ++f) {
+          const double xp = (f == 0 ? t + 0.5 : (double)t) * L.h;
+          double v = 0;
+          if (w > 0 && desc->abl_amp != 0) {
+            const double d = (w - xp > 0 ? w - xp : 0) + (xp - (len - w) > 0 ? xp - (len - w) : 0);
+            v = desc->abl_amp * (d / w) * (d / w);
+          }
+          t64[f * L.n[2] + t] = v;
+          t32[f * L.n[2] + t] = (float)v;
+        }
+      e |= hipMemcpy(L.ablz[0].p, t64.data(), t64.size() * 8, hipMemcpyHostToDevice) != hipSuccess;
+      e |= hipMemcpy(L.ablz[1].p, t32.data(), t32.size() * 4, hipMemcpyHostToDevice) != hipSuccess;
+    }
     if (e) {
       elh_destroy(H);
       return ELH_ERR_OOM;
@@ -322,7 +347,9 @@ extern "C" int elh_destroy(elh_handle* H) {
     LevelData& L = H->lv[l];
     release(L.lam); release(L.mu); release(L.rho); release(L.kap);
     release(L.mu32); release(L.rho32); release(L.kap32);
-    for (int p = 0; p < 2; ++p) { release(L.b[p]); release(L.x[p]); release(L.r[p]); release(L.kw[p]); }
+    for (int p = 0; p < 2; ++p) {
+      release(L.b[p]); release(L.x[p]); release(L.r[p]); release(L.kw[p]); release(L.ablz[p]);
+    }
     release(L.kc);
   }
   for (int p = 0; p < 2; ++p) {
@@ -458,8 +485,8 @@ static int stencil_choice(elh_handle* H, int l, bool shifted, bool adj, const vo
   }
   const LevelData& L = H->lv[l];
   std::vector<int> cand;
-  for (int zc : {4, 8, 16, 32, 64})
-    if (zc < L.n[2]) cand.push_back(zc);
+  for (int zc : {1, 2, 4, 8, 16, 32, 64})
+    if (zc < L.n[2] && (zc >= 4 || L.n[2] <= 64)) cand.push_back(zc);  // 1, 2 only on short columns
   if (L.n[2] <= 64) cand.push_back(L.n[2]);  // the whole column in one chunk
   int best = dflt;
   float tbest = 0;

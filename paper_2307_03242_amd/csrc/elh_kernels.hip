@@ -343,7 +343,9 @@ template <typename T>
 int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* x, int colour, double w, int nrhs,
                  hipStream_t st) {
   const int64_t work = (L.fs / L.n[0]) * ((L.n[0] + 1) / 2);
-  dim3 blk(256), grd((unsigned)((work + 255) / 256), nrhs);
+  // small (coarse) levels: 64-thread workgroups so that every CU gets work
+  const int bs = work < 256 * 256 ? 64 : 256;
+  dim3 blk(bs), grd((unsigned)((work + bs - 1) / bs), nrhs);
   const cx<T>* rp = (const cx<T>*)r;
   cx<T>* xp = (cx<T>*)x;
   if (dim == 3) {

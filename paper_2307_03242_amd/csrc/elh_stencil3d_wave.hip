@@ -110,6 +110,7 @@ template <typename T> struct W3Ctx {
   T beta, omb, ih, ih2, cn, omega2;
   bool has_abl;
   T h, len1, len2, len3, abl_w, abl_iw, abl_amp, gam;
+  const T* ablz;  // x_3 part of the absorbing layer per plane (centres, then lower faces)
   T gf;         // gamma (+alpha) + x_1 and x_2 parts of the layer at this wave's faces
 };
 
@@ -156,6 +157,7 @@ __device__ __forceinline__ void w3_setup(W3Ctx<T>& C, const LevelArgs<T>& L, con
   C.h = L.h; C.len1 = C.n1 * L.h; C.len2 = C.n2 * L.h; C.len3 = C.n3 * L.h;
   C.gam = L.gam;
   C.abl_w = L.abl_w; C.abl_iw = L.abl_iw; C.abl_amp = L.abl_amp;
+  C.ablz = L.ablz;
   // gamma~ at this wave's faces: x_1 / x_2 parts of the layer (the face of
   // u_k sits at a cell edge along x_k and at cell centres otherwise)
   C.gf = L.gam;
@@ -172,7 +174,8 @@ template <int K, typename T, typename TI, bool RESID>
 __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
   constexpr int CB = (int)sizeof(cx<T>), CBI = (int)sizeof(cx<TI>), RBY = (int)sizeof(T);
   const T q = T(0.25), hf = T(0.5);
-  const T beta = C.beta, omb = C.omb;
+  const T beta = C.beta;
+  const T oq = C.omb * q, oh = C.omb * hf;  // (1-beta)/4, (1-beta)/2 of the spread
   const int lane = threadIdx.x;
   const int n3 = C.n3;
   int vu[3], vi[3], vr[4];  // lane byte offsets: output/rhs fields, input fields, media
@@ -229,7 +232,11 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
   cx<T> PA, PB, Pbm;    // p at (c, t-1) / (c, t) ping-pong; p at (c-1, t)
   T MA[3], MB[3];       // mu at rows c-1, c, c+1 (planes t-1 / t ping-pong)
   T rhob[3];            // rho at rows c-1, c, c+1 (plane t)
-  const int t0 = C.z0 - 2;
+  // two warm-up planes, plus one more where the chunk starts on an odd plane:
+  // the loop below takes planes in pairs, and anchoring the pairs to even
+  // planes makes every plane go through the same copy of the step whatever
+  // the chunk length, so all chunk lengths give the same bits
+  const int t0 = C.z0 - 2 - (C.z0 & 1);
 #pragma unroll
   for (int r = 0; r < 3; ++r) UA[r] = UB[r] = czero<T>();
   WA = WB = Y3b = F3 = Wmp = czero<T>();
@@ -271,24 +278,21 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
       if (K == 2) rf[r] = hf * (rhob[r] + rhon[r]);
     }
     load_next(t + 2);
-    T a3 = T(0);
-    if (C.has_abl) {
-      const T xp = (K == 2 ? T(t) : T(t) + hf) * C.h;
-      a3 = absorb<T>(xp, C.len3, C.abl_w, C.abl_iw, C.abl_amp);
-    }
+    // x_3 part of gamma~ at this plane's faces (wave-uniform table entry)
+    const T a3 = C.has_abl ? C.ablz[(K == 2 ? n3 : 0) + min(max(t, 0), n3 - 1)] : T(0);
     const cx<T> Wn = rf[1] * Un[1];
     const cx<T> Wmpn = rf[0] * Un[0] + rf[2] * Un[2];
     // Y_3(t+1) = beta u + (1-beta) A_1 A_2 u at row c
     const cx<T> V = q * (Un[0] + Un[2]) + hf * Un[1];
-    const cx<T> Y3n = beta * Un[1] + omb * (q * (fromL(V) + fromR(V)) + hf * V);
+    const cx<T> Y3n = beta * Un[1] + oq * (fromL(V) + fromR(V)) + oh * V;
     // A_3 u(t) at rows c-1, c, c+1; Y_1(t) (row c) and Y_2(t) (three rows)
     cx<T> Z[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) Z[r] = q * (UO[r] + Un[r]) + hf * UC[r];
-    const cx<T> y1 = beta * UC[1] + omb * (q * (Z[0] + Z[2]) + hf * Z[1]);
+    const cx<T> y1 = beta * UC[1] + oq * (Z[0] + Z[2]) + oh * Z[1];
     cx<T> y2[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) y2[r] = beta * UC[r] + omb * (q * (fromL(Z[r]) + fromR(Z[r])) + hf * Z[r]);
+    for (int r = 0; r < 3; ++r) y2[r] = beta * UC[r] + oq * (fromL(Z[r]) + fromR(Z[r])) + oh * Z[r];
     const cx<T> d1lo = y1 - fromL(y1);
     const cx<T> d1hi = fromR(d1lo);
     const cx<T> d2lo = y2[1] - y2[0], d2hi = y2[2] - y2[1];
@@ -378,7 +382,8 @@ template <int K, typename T, bool RESID>
 __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
   constexpr int CB = (int)sizeof(cx<T>), RBY = (int)sizeof(T);
   const T q = T(0.25), hf = T(0.5);
-  const T beta = C.beta, omb = C.omb;
+  const T beta = C.beta;
+  const T oq = C.omb * q, oh = C.omb * hf;  // (1-beta)/4, (1-beta)/2 of the spread
   const int lane = threadIdx.x;
   const int n3 = C.n3;
   int vu[3], vr[4], vl[3];
@@ -414,9 +419,8 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
                 absorb<T>(x2, C.len2, C.abl_w, C.abl_iw, C.abl_amp);
     }
   }
-  auto a3of = [&](int z) {
-    if (!C.has_abl) return T(0);
-    return absorb<T>((K == 2 ? T(z) : T(z) + hf) * C.h, C.len3, C.abl_w, C.abl_iw, C.abl_amp);
+  auto a3of = [&](int z) {  // x_3 part of gamma~ at plane z's faces (table entry)
+    return C.has_abl ? C.ablz[(K == 2 ? n3 : 0) + min(max(z, 0), n3 - 1)] : T(0);
   };
   auto att = [&](T g, cx<T> u) { return mk(u.re - g * u.im, u.im + g * u.re); };  // (1 + i g) u
   auto A1 = [&](cx<T> v) { return q * (fromL(v) + fromR(v)) + hf * v; };
@@ -538,20 +542,20 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
 #pragma unroll
     for (int r = 0; r < 3; ++r) G1n[r] = mu1[r] * (K == 0 ? fromR(Un[r]) - Un[r] : Un[r] - fromL(Un[r]));
     const cx<T> X1n = q * (G1n[0] + G1n[2]) + hf * G1n[1];
-    const cx<T> SG1 = beta * G1b + omb * (q * (X1a + X1n) + hf * X1b);
+    const cx<T> SG1 = beta * G1b + oq * (X1a + X1n) + oh * X1b;
     cx<T> acc = K == 0 ? fromL(SG1) - SG1 : SG1 - fromR(SG1);
     // flux along x_2 at the lower / upper flux row, plane t+1
     const cx<T> G2ln = mu2l * (Un[1] - Un[0]), G2hn = mu2h * (Un[2] - Un[1]);
     const cx<T> Q2ln = A1(G2ln), Q2hn = A1(G2hn);
-    const cx<T> SG2l = beta * G2lb + omb * (q * (Q2la + Q2ln) + hf * Q2lb);
-    const cx<T> SG2h = beta * G2hb + omb * (q * (Q2ha + Q2hn) + hf * Q2hb);
+    const cx<T> SG2l = beta * G2lb + oq * (Q2la + Q2ln) + oh * Q2lb;
+    const cx<T> SG2h = beta * G2hb + oq * (Q2ha + Q2hn) + oh * Q2hb;
     acc += SG2l - SG2h;
     // flux along x_3 through the face between planes t and t+1
     cx<T> G3[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) G3[r] = mu3[r] * (Un[r] - UC[r]);
     const cx<T> V3 = q * (G3[0] + G3[2]) + hf * G3[1];
-    const cx<T> SG3n = beta * G3[1] + omb * A1(V3);
+    const cx<T> SG3n = beta * G3[1] + oq * (fromL(V3) + fromR(V3)) + oh * V3;
     acc += SG3 - SG3n;
     acc = C.ih2 * acc;
     // adjoint spread mass: rho_f of the output face times the spread of
@@ -568,20 +572,20 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
     cx<T> dv;
     if (K == 0) {
       const cx<T> A2n = q * (Pn[0] + Pn[2]) + hf * Pn[1];
-      const cx<T> SP = beta * Pc0 + omb * (q * (Pa0 + A2n) + hf * Pb0);
+      const cx<T> SP = beta * Pc0 + oq * (Pa0 + A2n) + oh * Pb0;
       acc += C.ih * (fromL(SP) - SP);
       dv = UC[1] - fromR(UC[1]);
       Pa0 = Pb0; Pb0 = A2n; Pc1 = Pc0; Pc0 = Pn[1];  // Pc1: p(c, t) for the p row
     } else if (K == 1) {
       const cx<T> A1m = A1(Pn[0]), A1c = A1(Pn[1]);
-      const cx<T> SPm = beta * Pc0 + omb * (q * (Pa0 + A1m) + hf * Pb0);
-      const cx<T> SPc = beta * Pc1 + omb * (q * (Pa1 + A1c) + hf * Pb1);
+      const cx<T> SPm = beta * Pc0 + oq * (Pa0 + A1m) + oh * Pb0;
+      const cx<T> SPc = beta * Pc1 + oq * (Pa1 + A1c) + oh * Pb1;
       acc += C.ih * (SPm - SPc);
       dv = UC[1] - UC[2];
       Pa0 = Pb0; Pb0 = A1m; Pa1 = Pb1; Pb1 = A1c; Pc0 = Pn[0]; Pc1 = Pn[1];
     } else {
       const cx<T> V = q * (Pn[0] + Pn[2]) + hf * Pn[1];
-      const cx<T> SPn = beta * Pn[1] + omb * A1(V);
+      const cx<T> SPn = beta * Pn[1] + oq * (fromL(V) + fromR(V)) + oh * V;
       acc += C.ih * (Pa0 - Pb0);
       dv = UC[1] - Un[1];
       Pa0 = Pb0; Pb0 = SPn;
