@@ -201,7 +201,11 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
   cx<TI> nu[3];
   cx<TI> npm, npc;
   T nmu[3], nrho[4], nrhoL;
+  T na3;  // x_3 part of gamma~ for plane z-1: a table entry fetched with the plane-z loads, as a
+          // vector load, so no wait on the scalar cache stalls the LDS hand-off
+  const __amdgpu_buffer_rsrc_t RABL = rsrc(C.ablz, C.has_abl ? 2 * n3 * RBY : 0);
   auto load_next = [&](int z) {
+    na3 = bload<T>(RABL, 0, ((K == 2 ? n3 : 0) + min(max(z - 1, 0), n3 - 1)) * RBY);
     const int so = zcl(z) * CBI, sr = zcl(z) * RBY;
 #pragma unroll
     for (int r = 0; r < 3; ++r) nu[r] = bload<cx<TI>>(C.RX[K], vi[r], so);
@@ -277,9 +281,8 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
       if (K == 1) rf[r] = hf * (nrho[r] + rhon[r]);
       if (K == 2) rf[r] = hf * (rhob[r] + rhon[r]);
     }
+    const T a3 = na3;  // x_3 part of gamma~ at this plane's faces
     load_next(t + 2);
-    // x_3 part of gamma~ at this plane's faces (wave-uniform table entry)
-    const T a3 = C.has_abl ? C.ablz[(K == 2 ? n3 : 0) + min(max(t, 0), n3 - 1)] : T(0);
     const cx<T> Wn = rf[1] * Un[1];
     const cx<T> Wmpn = rf[0] * Un[0] + rf[2] * Un[2];
     // Y_3(t+1) = beta u + (1-beta) A_1 A_2 u at row c
@@ -428,7 +431,10 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
   // loads in flight for the next plane
   cx<T> nu[3], np[3];
   T nmu[4], nrho[2], nmuL[3];
+  T na3;  // x_3 part of gamma~ for plane z (table entry, loaded with plane z)
+  const __amdgpu_buffer_rsrc_t RABL = rsrc(C.ablz, C.has_abl ? 2 * n3 * RBY : 0);
   auto load_next = [&](int z) {
+    na3 = bload<T>(RABL, 0, ((K == 2 ? n3 : 0) + min(max(z, 0), n3 - 1)) * RBY);
     const int so = zcl(z) * CB, sr = zcl(z) * RBY;
 #pragma unroll
     for (int r = 0; r < 3; ++r) nu[r] = bload<cx<T>>(C.RX[K], vu[r], so);
@@ -499,7 +505,7 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
     for (int r = 0; r < 3; ++r) munL[r] = K == 0 ? nmuL[r] : T(0);
     rhon0 = K == 1 ? nrho[0] : nrho[1];
     rhon1 = nrho[1];
-    const T a3n = a3of(tn);
+    const T a3n = na3;
     load_next(t + 2);
 
     // edge/cell mu of this component's fluxes at plane t+1 (and between t, t+1)
