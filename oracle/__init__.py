@@ -19,6 +19,9 @@ Contents (each module cites the passage it follows):
   cycle      coarse hierarchy, two-grid / V-cycle (Algorithm 1), coarsest
              solves
   krylov     flexible GMRES(m) with right preconditioning
+  kaczmarz   the paper's 3D coarsest-grid solver: Schur complement of the
+             pressure, FGMRES preconditioned by hybrid (component-averaged,
+             sub-region parallel) Kaczmarz sweeps
   adjoint    adjoint solve, misfit and parameter gradient
   symbols    closed-form Fourier symbols of the constant-coefficient blocks
   lfa        two-grid local Fourier analysis (Section 4)

@@ -22,8 +22,9 @@ Test infrastructure (see the package header).
   LU, the paper's 2D choice), 'relax' (a fixed number of red-black Vanka
   sweeps from zero), or 'krylov' (restarted GMRES preconditioned by a
   fixed number of red-black Vanka sweeps, with a fixed iteration budget
-  and an optional residual-drop stop), the parallel stand-in for the
-  paper's Kaczmarz-preconditioned FGMRES in 3D.
+  and an optional residual-drop stop), or 'kaczmarz' (the paper's 3D
+  choice: FGMRES on the Schur complement of the pressure preconditioned by
+  hybrid Kaczmarz sweeps, `oracle.kaczmarz`).
 """
 import numpy as np
 import scipy.sparse.linalg as spla
@@ -33,6 +34,7 @@ from . import operator as O
 from . import transfer as T
 from .smoother import Vanka
 from .krylov import fgmres
+from .kaczmarz import SchurKaczmarzSolver
 
 
 def coarsen_media(a, dim):
@@ -61,7 +63,7 @@ class CycleParams:
     def __init__(self, levels=2, alpha=0.1, damping=(0.55, 0.35, 0.25, 0.25),
                  nu1=1, nu2=1, coarse="direct", coarse_sweeps=2,
                  coarse_restart=5, coarse_maxit=10, coarse_rtol=0.0,
-                 coarse_damping=None, calls=1):
+                 coarse_damping=None, calls=1, kacz_box=4):
         # calls: 1 V-cycle, 2 W-cycle, 3 K-cycle (two Krylov-accelerated calls)
         self.levels = levels
         self.calls = calls
@@ -74,6 +76,7 @@ class CycleParams:
         self.coarse_maxit = coarse_maxit
         self.coarse_rtol = coarse_rtol
         self.coarse_damping = coarse_damping
+        self.kacz_box = kacz_box
 
     def w(self, l):
         return self.damping[min(l, len(self.damping) - 1)]
@@ -81,6 +84,8 @@ class CycleParams:
     def wc(self):
         if self.coarse_damping is not None:
             return self.coarse_damping
+        if self.coarse == "kaczmarz":
+            return 0.8  # the paper's Kaczmarz relaxation (Section 5.3)
         return self.w(self.levels - 1)
 
 
@@ -106,6 +111,7 @@ class Hierarchy:
         self.P = [T.prolongation_matrix(lv) for lv in self.levels[:-1]]
         self.smoothers = [Vanka(lv, A) for lv, A in zip(self.levels, self.A)]
         self._lu = None
+        self._kz = None
 
     # -- coarsest-level solve -------------------------------------------------
     def _relax_from_zero(self, l, b, sweeps, w):
@@ -130,6 +136,13 @@ class Hierarchy:
                           restart=p.coarse_restart, tol=p.coarse_rtol,
                           maxit=p.coarse_maxit)
             return x
+        if p.coarse == "kaczmarz":
+            if self._kz is None:
+                self._kz = SchurKaczmarzSolver(self.levels[l], self.A[l], box=p.kacz_box, omega=p.wc(),
+                                               sweeps=p.coarse_sweeps, restart=p.coarse_restart,
+                                               rtol=p.coarse_rtol, maxit=p.coarse_maxit,
+                                               adjoint=self.adjoint)
+            return self._kz.solve(b)
         raise ValueError(p.coarse)
 
     # -- cycle ------------------------------------------------------------------
