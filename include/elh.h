@@ -66,7 +66,11 @@ enum { ELH_COARSE_KRYLOV = 0,  /* restarted GMRES preconditioned by red-black
                                   Vanka sweeps, fixed budget / residual drop */
        ELH_COARSE_DENSE = 1,   /* exact solve (dense inverse built at setup;
                                   the paper's LU choice for 2D)             */
-       ELH_COARSE_RELAX = 2    /* fixed number of red-black Vanka sweeps    */ };
+       ELH_COARSE_RELAX = 2,   /* fixed number of red-black Vanka sweeps    */
+       ELH_COARSE_KACZMARZ = 3 /* the paper's 3D choice: p eliminated through
+                                  its diagonal block, FGMRES on the Schur
+                                  complement preconditioned by hybrid
+                                  Kaczmarz sweeps (see elh_kaczmarz)        */ };
 
 typedef struct {
   int dim;              /* 2 or 3                                              */
@@ -90,14 +94,24 @@ typedef struct {
                            below Algorithm 1)                                 */
   double damping[8];    /* Vanka damping w per level (Section 5.2)            */
   int coarse_mode;      /* ELH_COARSE_*                                       */
-  int coarse_sweeps;    /* Vanka sweeps per coarse relaxation/preconditioning */
-  int coarse_restart;   /* inner GMRES restart length (KRYLOV)                */
-  int coarse_maxit;     /* inner GMRES iterations budget (KRYLOV)             */
-  double coarse_rtol;   /* inner residual-drop stop, 0 = always full budget   */
+  int coarse_sweeps;    /* Vanka sweeps per coarse relaxation/preconditioning;
+                           KACZMARZ: hybrid Kaczmarz sweeps per
+                           preconditioning (paper: 10)                        */
+  int coarse_restart;   /* inner GMRES restart length (KRYLOV, KACZMARZ;
+                           paper: 5)                                          */
+  int coarse_maxit;     /* inner GMRES iterations budget (KRYLOV, KACZMARZ;
+                           paper: 25, i.e. at most 250 Kaczmarz sweeps)      */
+  double coarse_rtol;   /* inner residual-drop stop, 0 = always full budget
+                           (paper, KACZMARZ: 0.1)                             */
   double coarse_damping;/* Vanka damping on the coarsest level (<=0: use
-                           damping[levels-1])                                 */
+                           damping[levels-1]); KACZMARZ: the relaxation of
+                           the row projections (<=0: 0.8, the paper's)        */
   int precond_dtype;    /* ELH_C128: float64 cycle; ELH_C64: float32 cycle
                            inside the float64 Krylov solve (Section 5.3)      */
+  int kacz_box;         /* KACZMARZ: sub-regions are boxes of kacz_box^dim
+                           cells (<= 0: 4); the private copy of a sub-region,
+                           dim*(kacz_box+4)^dim complex float64, must fit in
+                           64 KiB of LDS (3D: kacz_box <= 6)                  */
 } elh_desc;
 
 typedef struct {
@@ -172,6 +186,25 @@ int elh_relax(elh_handle* h, int level, int flags, int dtype, int nrhs,
  * levels-1. */
 int elh_coarse_solve(elh_handle* h, int flags, int dtype, int nrhs,
                      const void* b, void* x);
+
+/* The preconditioner of the ELH_COARSE_KACZMARZ coarsest solve (Section
+ * 3.2, "Coarsest grid solution"; parameters in Section 5.3), on level
+ * levels-1, for a handle created with that mode: x = `sweeps` hybrid
+ * Kaczmarz sweeps from x = 0 on S x_u = b_u, where
+ * S = A_uu - A_up diag(A_pp)^-1 A_pu is the Schur complement of the
+ * pressure of A = H_s (ELH_ADJOINT: of H_s^H, i.e. S^H).  One sweep: every
+ * sub-region (a box of kacz_box^dim cells; a displacement unknown belongs
+ * to the box holding its storage index) starts from the current iterate
+ * and projects it, row by row in ascending storage order over its own rows
+ * a_i, onto  x <- x + w (b_i - a_i x) / ||a_i||^2 conj(a_i)  (w =
+ * coarse_damping, or 0.8); each unknown then takes the mean of the copies of
+ * the sub-regions whose rows reach it through the stencil pattern of S.
+ * b, x: device vectors in storage layout (nrhs, dim+1, n_d..n_1) of the
+ * coarsest level in dtype; the pressure entries of b are ignored, those of
+ * x are set to zero.  nrhs <= 64.  Errors: ELH_ERR_ARG (mode, sizes),
+ * ELH_ERR_OOM (work buffers), ELH_ERR_HIP (launch). */
+int elh_kaczmarz(elh_handle* h, int flags, int dtype, int nrhs, int sweeps,
+                 const void* b, void* x);
 
 /* x = V(nu1,nu2)-cycle (cycle_calls = 1), W-cycle (2) or K-cycle (3)
  * approximation of H_s^{-1} b on level 0 from a zero initial guess

@@ -9,11 +9,11 @@ ELH_OK, ELH_NOT_CONVERGED = 0, 1
 ELH_ERR_ARG, ELH_ERR_HIP, ELH_ERR_NUMERIC, ELH_ERR_OOM, ELH_ERR_STATE = -1, -2, -3, -4, -5
 ELH_C64, ELH_C128 = 1, 2
 ELH_SHIFTED, ELH_ADJOINT = 1, 2
-ELH_COARSE_KRYLOV, ELH_COARSE_DENSE, ELH_COARSE_RELAX = 0, 1, 2
+ELH_COARSE_KRYLOV, ELH_COARSE_DENSE, ELH_COARSE_RELAX, ELH_COARSE_KACZMARZ = 0, 1, 2, 3
 
 EXPORTED = [
     "elh_create", "elh_set_media", "elh_destroy", "elh_apply", "elh_residual",
-    "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_coarse_solve",
+    "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_coarse_solve", "elh_kaczmarz",
     "elh_vcycle", "elh_solve", "elh_solve_adjoint", "elh_solve_batch", "elh_gradient",
     "elh_level_info", "elh_stencil_choice", "elh_status_string", "elh_last_error",
 ]
@@ -32,6 +32,7 @@ class Desc(ctypes.Structure):
         ("coarse_restart", ctypes.c_int), ("coarse_maxit", ctypes.c_int),
         ("coarse_rtol", ctypes.c_double), ("coarse_damping", ctypes.c_double),
         ("precond_dtype", ctypes.c_int),
+        ("kacz_box", ctypes.c_int),
     ]
 
 
@@ -71,6 +72,7 @@ def load():
         "elh_prolong_add": [H, ip, ip, ip, vp, vp],
         "elh_relax": [H, ip, ip, ip, ip, ip, vp, vp],
         "elh_coarse_solve": [H, ip, ip, ip, vp, vp],
+        "elh_kaczmarz": [H, ip, ip, ip, ip, vp, vp],
         "elh_vcycle": [H, ip, ip, ip, vp, vp],
         "elh_solve": [H, ip, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
         "elh_solve_adjoint": [H, ip, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],

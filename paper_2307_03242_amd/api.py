@@ -41,6 +41,12 @@ class Problem:
     device (copied to the current GPU).  Lengths (h, abl_width) are in
     physical units.  cycle: 'V', 'W' or 'K' (the two coarse calls of every
     level precondition two flexible-GCR steps on the coarse system).
+    coarse_mode: 'krylov' (GMRES preconditioned by Vanka sweeps), 'dense',
+    'relax', or 'kaczmarz' (the paper's 3D solver: FGMRES on the Schur
+    complement of the pressure preconditioned by hybrid Kaczmarz sweeps over
+    sub-regions of kacz_box^d cells; the paper uses coarse_sweeps=10,
+    coarse_restart=5, coarse_maxit=25, coarse_rtol=0.1 and relaxation
+    coarse_damping=0.8, the default when coarse_damping <= 0).
     """
 
     def __init__(self, lam, mu, rho, h=1.0, omega=1.0, gamma=0.01, alpha=0.3,
@@ -48,7 +54,7 @@ class Problem:
                  nu2=1, cycle='V', damping=(0.55, 0.35, 0.25), coarse_mode="krylov",
                  coarse_sweeps=2, coarse_restart=5, coarse_maxit=10,
                  coarse_rtol=0.0, coarse_damping=0.0, precond_dtype=torch.complex128,
-                 device=None):
+                 kacz_box=4, device=None):
         self.lib = L.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         lam = torch.as_tensor(lam, dtype=torch.float64).to(self.device).contiguous()
@@ -74,11 +80,13 @@ class Problem:
             damping.append(damping[-1])
         for i in range(8):
             d.damping[i] = damping[i]
-        modes = {"krylov": L.ELH_COARSE_KRYLOV, "dense": L.ELH_COARSE_DENSE, "relax": L.ELH_COARSE_RELAX}
+        modes = {"krylov": L.ELH_COARSE_KRYLOV, "dense": L.ELH_COARSE_DENSE, "relax": L.ELH_COARSE_RELAX,
+                 "kaczmarz": L.ELH_COARSE_KACZMARZ}
         d.coarse_mode = modes[coarse_mode]
         d.coarse_sweeps, d.coarse_restart, d.coarse_maxit = coarse_sweeps, coarse_restart, coarse_maxit
         d.coarse_rtol, d.coarse_damping = coarse_rtol, coarse_damping
         d.precond_dtype = L.ELH_C64 if precond_dtype == torch.complex64 else L.ELH_C128
+        d.kacz_box = kacz_box
         self.desc = d
         self.levels = levels
         self._media = (lam, mu, rho)
@@ -194,6 +202,16 @@ class Problem:
         x = torch.empty_like(b)
         L.check(self.lib.elh_coarse_solve(self.handle, self._flags(False, adjoint), _dtype_code(b), nrhs,
                                           _ptr(b), _ptr(x)))
+        return x
+
+    def kaczmarz(self, b, sweeps, adjoint=False):
+        """`sweeps` hybrid Kaczmarz sweeps from zero on the coarsest level's
+        Schur complement system (the preconditioner of coarse_mode
+        'kaczmarz'); pressure entries of b are ignored, of the result zero."""
+        nrhs = self._vec(b, self.levels - 1)
+        x = torch.empty_like(b)
+        L.check(self.lib.elh_kaczmarz(self.handle, self._flags(False, adjoint), _dtype_code(b), nrhs, sweeps,
+                                      _ptr(b), _ptr(x)))
         return x
 
     def vcycle(self, b, adjoint=False):

@@ -94,6 +94,17 @@ struct KrylovWS {
   DevBuf V, Z, w, t;
 };
 
+// Hybrid Kaczmarz coarsest solve: rows of the Schur complement in the slot
+// pattern, sub-region gather lists and work buffers.
+struct KaczData {
+  int ns = 0, box = 0, nreg = 0, ls = 0;
+  int E[3] = {1, 1, 1}, nb[3] = {1, 1, 1};
+  DevBuf val[2][2], inv[2][2];             // [adjoint][precision]
+  DevBuf tab[2], dl[2], gptr[2], gent[2];  // [adjoint]
+  DevBuf app[2];                           // A_pp per cell, [precision]
+  DevBuf scr, t, y, bs;                    // solve work
+};
+
 struct GraphEntry {
   int prec, adj, nrhs;
   const void* in;
@@ -111,6 +122,7 @@ struct elh_handle {
   DevBuf part, dots, coef, tmpvec;
   DevBuf gstate, gpart, gdots, gnrm, gcoef, gscale, ones;  // device-resident GMRES
   DevBuf dq64, dq32;                                        // dense coarsest inverse (Q = inv(H_s^T))
+  KaczData kz;                                              // hybrid Kaczmarz coarsest solve
   int64_t dn = 0;
   hipStream_t cap = nullptr;                               // stream used only to record graphs
   std::vector<GraphEntry> graphs;
@@ -181,10 +193,23 @@ static int check_desc(const elh_desc* d) {
   if (d->nu1 < 0 || d->nu2 < 0) return fail(ELH_ERR_ARG, "nu1/nu2 must be >= 0");
   if (d->cycle_calls < 1 || d->cycle_calls > 3)
     return fail(ELH_ERR_ARG, "cycle_calls must be 1 (V), 2 (W) or 3 (K)");
-  if (d->coarse_mode < 0 || d->coarse_mode > 2) return fail(ELH_ERR_ARG, "bad coarse_mode");
+  if (d->coarse_mode < 0 || d->coarse_mode > 3) return fail(ELH_ERR_ARG, "bad coarse_mode");
   if (d->coarse_mode != ELH_COARSE_DENSE && d->coarse_sweeps < 1) return fail(ELH_ERR_ARG, "coarse_sweeps must be >= 1");
-  if (d->coarse_mode == ELH_COARSE_KRYLOV && (d->coarse_restart < 1 || d->coarse_maxit < 1))
+  if ((d->coarse_mode == ELH_COARSE_KRYLOV || d->coarse_mode == ELH_COARSE_KACZMARZ) &&
+      (d->coarse_restart < 1 || d->coarse_maxit < 1))
     return fail(ELH_ERR_ARG, "coarse_restart/coarse_maxit must be >= 1");
+  if (d->coarse_mode == ELH_COARSE_KACZMARZ) {
+    if (d->kacz_box < 0) return fail(ELH_ERR_ARG, "kacz_box must be >= 0");
+    const int box = d->kacz_box > 0 ? d->kacz_box : 4;
+    int64_t ls = d->dim;
+    for (int a = 0; a < d->dim; ++a) ls *= box + 4;
+    if (ls * 16 > (int64_t)KACZ_MAX_LDS)
+      return fail(ELH_ERR_ARG, "kacz_box %d: the private copy of a sub-region exceeds %zu bytes of LDS", box,
+                  KACZ_MAX_LDS);
+    int64_t fs = 1;
+    for (int a = 0; a < d->dim; ++a) fs *= d->n[a] >> (d->levels - 1);
+    if (fs > 64 * 64 * 64) return fail(ELH_ERR_ARG, "Kaczmarz coarsest solve needs at most 64^3 coarsest cells");
+  }
   if (d->coarse_restart + 1 > MAXDOT) return fail(ELH_ERR_ARG, "coarse_restart too large");
   if (d->precond_dtype != ELH_C64 && d->precond_dtype != ELH_C128) return fail(ELH_ERR_ARG, "bad precond_dtype");
   if (d->abl_width < 0) return fail(ELH_ERR_ARG, "abl_width must be >= 0");
@@ -218,6 +243,7 @@ static int build_hierarchy(elh_handle* H, const double* lam, const double* mu, c
 // Gauss-Jordan inversion of H_s^T on the device.
 static constexpr int64_t DENSE_MAX = 8192;
 static int build_dense(elh_handle* H);
+static int build_kaczmarz(elh_handle* H);
 
 static void tune_load(elh_handle* H);
 static int tune_key(int l, int prec, int iprec, bool resid, bool adj, int nrhs);
@@ -321,6 +347,7 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
   }
   rc = build_hierarchy(H, lam, mu, rho);
   if (!rc && desc->coarse_mode == ELH_COARSE_DENSE) rc = build_dense(H);
+  if (!rc && desc->coarse_mode == ELH_COARSE_KACZMARZ) rc = build_kaczmarz(H);
   if (rc) {
     elh_destroy(H);
     return rc;
@@ -336,6 +363,7 @@ extern "C" int elh_set_media(elh_handle* H, const double* lam, const double* mu,
   if (!lam || !mu || !rho) return fail(ELH_ERR_ARG, "media pointers must be non-NULL");
   int rc = build_hierarchy(H, lam, mu, rho);
   if (!rc && H->d.coarse_mode == ELH_COARSE_DENSE) rc = build_dense(H);
+  if (!rc && H->d.coarse_mode == ELH_COARSE_KACZMARZ) rc = build_kaczmarz(H);
   return rc;
 }
 
@@ -359,6 +387,12 @@ extern "C" int elh_destroy(elh_handle* H) {
   release(H->part); release(H->dots); release(H->coef); release(H->tmpvec);
   release(H->gstate); release(H->gpart); release(H->gdots); release(H->gnrm); release(H->gcoef);
   release(H->gscale); release(H->ones); release(H->dq64); release(H->dq32);
+  for (int a = 0; a < 2; ++a) {
+    for (int p = 0; p < 2; ++p) { release(H->kz.val[a][p]); release(H->kz.inv[a][p]); }
+    release(H->kz.tab[a]); release(H->kz.dl[a]); release(H->kz.gptr[a]); release(H->kz.gent[a]);
+    release(H->kz.app[a]);
+  }
+  release(H->kz.scr); release(H->kz.t); release(H->kz.y); release(H->kz.bs);
   for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
   H->graphs.clear();
   if (H->cap) (void)hipStreamDestroy(H->cap);
@@ -861,6 +895,251 @@ static int build_dense(elh_handle* H) {
   return rc;
 }
 
+// Hybrid Kaczmarz coarsest solve, setup.  The entries of A = H_s on the
+// coarsest level come from applying it (float64 point-wise kernel) to
+// (dim+1)*3^dim probe vectors: probe (f, r) holds ones on the unknowns of
+// field f whose storage index is congruent to r modulo 3 on every axis.
+// Every column of A reaches rows within one cell of it, so the entry of
+// row i and column j (|i - j| <= 1 cell per axis) is the value of row i
+// in the probe that holds j.  From those, per displacement row and slot of
+// the pattern,
+//   S_ij = [A_uu]_ij - sum_m [A_up]_im [A_pu]_mj / [A_pp]_mm,
+// the adjoint rows being conj(S_ji).  Slot pattern of the row of u_k
+// towards u_l (offsets of the column's storage index): the 3^dim box when
+// l = k; otherwise o_l in {0, 1}, o_k in {-2..1}, the remaining axis in
+// {-1, 0, 1}; adjoint rows take the negated pattern of u_l towards u_k.
+static void kacz_slots(int dim, int k, bool adj, std::vector<int>& tab) {
+  for (int l = 0; l < dim; ++l) {
+    const int kk = adj ? l : k, ll = adj ? k : l;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+      if (kk == ll) { lo[a] = -1; hi[a] = 1; }
+      else if (a == ll) { lo[a] = 0; hi[a] = 1; }
+      else if (a == kk) { lo[a] = -2; hi[a] = 1; }
+      else { lo[a] = -1; hi[a] = 1; }
+    }
+    const int sg = adj ? -1 : 1;
+    for (int o2 = lo[2]; o2 <= hi[2]; ++o2)
+      for (int o1 = lo[1]; o1 <= hi[1]; ++o1)
+        for (int o0 = lo[0]; o0 <= hi[0]; ++o0) {
+          tab.push_back(l);
+          tab.push_back(sg * o0);
+          tab.push_back(sg * o1);
+          tab.push_back(sg * o2);
+        }
+  }
+}
+
+static int build_kaczmarz(elh_handle* H) {
+  const int l = H->nlev - 1;
+  const LevelData& L = H->lv[l];
+  const int dim = H->d.dim;
+  const int64_t fs = L.fs, vs = L.vs, nu = (int64_t)dim * fs;
+  const int n0 = L.n[0], n1 = L.n[1], n2 = L.n[2];
+  KaczData& K = H->kz;
+  K.box = H->d.kacz_box > 0 ? H->d.kacz_box : 4;
+  const int P = dim == 3 ? 27 : 9;
+  const int np = (dim + 1) * P;
+  auto lin = [&](int x, int y, int z) { return ((int64_t)z * n1 + y) * n0 + x; };
+  auto res3 = [&](int x, int y, int z) { return x % 3 + 3 * (y % 3) + 9 * (z % 3); };
+  // probes and their images
+  std::vector<double> he((size_t)np * vs * 2, 0.0);
+  for (int f = 0; f <= dim; ++f)
+    for (int z = 0; z < n2; ++z)
+      for (int y = 0; y < n1; ++y)
+        for (int x = 0; x < n0; ++x) {
+          const int c[3] = {x, y, z};
+          if (f < dim && c[f] == 0) continue;
+          const int64_t p = (int64_t)f * P + res3(x, y, z);
+          he[2 * ((size_t)p * vs + f * fs + lin(x, y, z))] = 1.0;
+        }
+  DevBuf E, Y;
+  int rc = 0;
+  if (ensure(E, he.size() * 8) || ensure(Y, he.size() * 8)) {
+    release(E); release(Y);
+    return ELH_ERR_OOM;
+  }
+  hipStream_t st = H->st;
+  if (hipMemcpy(E.p, he.data(), he.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    rc = fail(ELH_ERR_HIP, "probe upload failed");
+  if (!rc) rc = launch_apply<double>(largs<double>(H, l, true), dim, false, E.p, nullptr, Y.p, np, st);
+  if (rc > 0) rc = fail(ELH_ERR_HIP, "probe apply failed");
+  std::vector<double> hy(he.size());
+  if (!rc && (hipStreamSynchronize(st) != hipSuccess ||
+              hipMemcpy(hy.data(), Y.p, hy.size() * 8, hipMemcpyDeviceToHost) != hipSuccess))
+    rc = fail(ELH_ERR_HIP, "probe download failed");
+  release(E); release(Y);
+  if (rc) return rc;
+  // A(F, c; f, c'), |c - c'| <= 1 cell per axis
+  auto A = [&](int F, const int* c, int f, const int* cp) {
+    const size_t p = (size_t)f * P + res3(cp[0], cp[1], cp[2]);
+    const size_t i = p * vs + F * fs + lin(c[0], c[1], c[2]);
+    return zd(hy[2 * i], hy[2 * i + 1]);
+  };
+  auto inside = [&](const int* c) {
+    return c[0] >= 0 && c[0] < n0 && c[1] >= 0 && c[1] < n1 && c[2] >= 0 && c[2] < n2;
+  };
+  auto cheb1 = [&](const int* a, const int* b) {
+    return abs(a[0] - b[0]) <= 1 && abs(a[1] - b[1]) <= 1 && abs(a[2] - b[2]) <= 1;
+  };
+  const int rz = dim == 3 ? 1 : 0;
+  // A_pp per cell
+  std::vector<zd> app(fs);
+  for (int z = 0; z < n2; ++z)
+    for (int y = 0; y < n1; ++y)
+      for (int x = 0; x < n0; ++x) {
+        const int c[3] = {x, y, z};
+        app[lin(x, y, z)] = A(dim, c, dim, c);
+        if (app[lin(x, y, z)] == zd(0, 0)) return fail(ELH_ERR_NUMERIC, "zero pressure diagonal");
+      }
+  // nonzero A_up couplings of every displacement row: (cell, value)
+  std::vector<std::vector<std::pair<int64_t, zd>>> up(nu);
+  for (int k = 0; k < dim; ++k)
+    for (int z = 0; z < n2; ++z)
+      for (int y = 0; y < n1; ++y)
+        for (int x = 0; x < n0; ++x) {
+          const int c[3] = {x, y, z};
+          if (c[k] == 0) continue;
+          auto& lst = up[k * fs + lin(x, y, z)];
+          for (int dz = -rz; dz <= rz; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                const int m[3] = {x + dx, y + dy, z + dz};
+                if (!inside(m)) continue;
+                const zd a = A(k, c, dim, m);
+                if (a != zd(0, 0)) lst.push_back({lin(m[0], m[1], m[2]), a});
+              }
+        }
+  // forward Schur entry of row (kr, cr), column (kc, cc)
+  auto Sf = [&](int kr, const int* cr, int kc, const int* cc) {
+    zd v(0, 0);
+    if (kr == kc && cheb1(cr, cc)) v = A(kr, cr, kc, cc);
+    for (const auto& e : up[kr * fs + lin(cr[0], cr[1], cr[2])]) {
+      const int64_t mc = e.first;
+      const int m[3] = {(int)(mc % n0), (int)((mc / n0) % n1), (int)(mc / ((int64_t)n0 * n1))};
+      if (!cheb1(m, cc)) continue;
+      v -= e.second * A(dim, m, kc, cc) / app[mc];
+    }
+    return v;
+  };
+  // sub-regions and private copies
+  int64_t nreg = 1, ee = 1;
+  for (int a = 0; a < 3; ++a) {
+    K.nb[a] = a < dim ? (L.n[a] + K.box - 1) / K.box : 1;
+    K.E[a] = a < dim ? K.box + 4 : 1;
+    nreg *= K.nb[a];
+    ee *= K.E[a];
+  }
+  K.nreg = (int)nreg;
+  K.ls = (int)(dim * ee);
+  for (int adj = 0; adj < 2; ++adj) {
+    std::vector<int> tab;
+    for (int k = 0; k < dim; ++k) kacz_slots(dim, k, adj != 0, tab);
+    const int ns = (int)(tab.size() / 4 / dim);
+    K.ns = ns;
+    std::vector<int> dl((size_t)dim * ns);
+    for (int k = 0; k < dim; ++k)
+      for (int q = 0; q < ns; ++q) {
+        const int* t = &tab[(size_t)(k * ns + q) * 4];
+        dl[(size_t)k * ns + q] = (int)(t[0] * ee + (t[3] * K.E[1] + t[2]) * K.E[0] + t[1]);
+      }
+    // rows
+    std::vector<double> v64((size_t)nu * ns * 2, 0.0), i64(nu, 0.0);
+    std::vector<float> v32((size_t)nu * ns * 2, 0.0f), i32(nu, 0.0f);
+    for (int k = 0; k < dim; ++k)
+      for (int z = 0; z < n2; ++z)
+        for (int y = 0; y < n1; ++y)
+          for (int x = 0; x < n0; ++x) {
+            const int c[3] = {x, y, z};
+            if (c[k] == 0) continue;
+            const int64_t row = k * fs + lin(x, y, z);
+            double nrm = 0;
+            for (int q = 0; q < ns; ++q) {
+              const int* t = &tab[(size_t)(k * ns + q) * 4];
+              const int lc = t[0];
+              const int cc[3] = {x + t[1], y + t[2], z + t[3]};
+              if (!inside(cc) || cc[lc] == 0) continue;
+              const zd v = adj ? std::conj(Sf(lc, cc, k, c)) : Sf(k, c, lc, cc);
+              const size_t o = ((size_t)row * ns + q) * 2;
+              v64[o] = v.real();
+              v64[o + 1] = v.imag();
+              v32[o] = (float)v.real();
+              v32[o + 1] = (float)v.imag();
+              nrm += std::norm(v);
+            }
+            i64[row] = nrm > 0 ? 1.0 / nrm : 0.0;
+            i32[row] = (float)i64[row];
+          }
+    // gather lists: for each unknown, the (sub-region, private index) pairs
+    // of the sub-regions whose rows reach it, sub-regions ascending
+    std::vector<std::vector<std::pair<int, int>>> lists(nu);
+    std::vector<char> mark(K.ls);
+    for (int r = 0; r < K.nreg; ++r) {
+      const int br[3] = {r % K.nb[0], (r / K.nb[0]) % K.nb[1], r / (K.nb[0] * K.nb[1])};
+      int lo[3], c0[3], c1[3];
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = a < dim ? br[a] * K.box - 2 : 0;
+        c0[a] = a < dim ? br[a] * K.box : 0;
+        c1[a] = a < dim ? std::min(c0[a] + K.box, L.n[a]) : 1;
+      }
+      std::fill(mark.begin(), mark.end(), 0);
+      for (int k = 0; k < dim; ++k)
+        for (int z = c0[2]; z < c1[2]; ++z)
+          for (int y = c0[1]; y < c1[1]; ++y)
+            for (int x = c0[0]; x < c1[0]; ++x) {
+              const int c[3] = {x, y, z};
+              if (c[k] == 0) continue;
+              for (int q = 0; q < ns; ++q) {
+                const int* t = &tab[(size_t)(k * ns + q) * 4];
+                const int lc = t[0];
+                const int cc[3] = {x + t[1], y + t[2], z + t[3]};
+                if (!inside(cc) || cc[lc] == 0) continue;
+                const int li = (int)(lc * ee + ((cc[2] - lo[2]) * K.E[1] + (cc[1] - lo[1])) * K.E[0] + (cc[0] - lo[0]));
+                if (mark[li]) continue;
+                mark[li] = 1;
+                lists[lc * fs + lin(cc[0], cc[1], cc[2])].push_back({r, li});
+              }
+            }
+    }
+    std::vector<int> gptr(nu + 1, 0), gent;
+    for (int64_t j = 0; j < nu; ++j) {
+      gptr[j + 1] = gptr[j] + (int)lists[j].size();
+      for (const auto& e : lists[j]) {
+        gent.push_back(e.first);
+        gent.push_back(e.second);
+      }
+    }
+    if (gent.empty()) gent.push_back(0);
+    if (ensure(K.val[adj][0], v64.size() * 8) || ensure(K.val[adj][1], v32.size() * 4) ||
+        ensure(K.inv[adj][0], i64.size() * 8) || ensure(K.inv[adj][1], i32.size() * 4) ||
+        ensure(K.tab[adj], tab.size() * 4) || ensure(K.dl[adj], dl.size() * 4) ||
+        ensure(K.gptr[adj], gptr.size() * 4) || ensure(K.gent[adj], gent.size() * 4))
+      return ELH_ERR_OOM;
+    if (hipMemcpy(K.val[adj][0].p, v64.data(), v64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(K.val[adj][1].p, v32.data(), v32.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(K.inv[adj][0].p, i64.data(), i64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(K.inv[adj][1].p, i32.data(), i32.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(K.tab[adj].p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(K.dl[adj].p, dl.data(), dl.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(K.gptr[adj].p, gptr.data(), gptr.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(K.gent[adj].p, gent.data(), gent.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(ELH_ERR_HIP, "upload of the Kaczmarz rows failed");
+  }
+  std::vector<double> a64(2 * fs);
+  std::vector<float> a32(2 * fs);
+  for (int64_t c = 0; c < fs; ++c) {
+    a64[2 * c] = app[c].real();
+    a64[2 * c + 1] = app[c].imag();
+    a32[2 * c] = (float)app[c].real();
+    a32[2 * c + 1] = (float)app[c].imag();
+  }
+  if (ensure(K.app[0], a64.size() * 8) || ensure(K.app[1], a32.size() * 4)) return ELH_ERR_OOM;
+  if (hipMemcpy(K.app[0].p, a64.data(), a64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(K.app[1].p, a32.data(), a32.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(ELH_ERR_HIP, "upload of the pressure diagonal failed");
+  return 0;
+}
+
 // Fixed-budget restarted GMRES with all bookkeeping on the device (no host
 // synchronisation, graph-capturable).  Same algorithm as gmres() with
 // rtol = 0: classical Gram-Schmidt, complex Givens, restart every m steps,
@@ -910,6 +1189,87 @@ static int gmres_device(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ
 }
 
 // ---------------------------------------------------------------------------
+// hybrid Kaczmarz coarsest solve
+// ---------------------------------------------------------------------------
+template <typename T>
+static KaczArgs<T> kacz_args(const elh_handle* H, bool adj) {
+  const KaczData& K = H->kz;
+  const LevelData& L = H->lv[H->nlev - 1];
+  const int p = sizeof(T) == 8 ? 0 : 1, a = adj ? 1 : 0;
+  KaczArgs<T> k;
+  k.dim = H->d.dim;
+  for (int i = 0; i < 3; ++i) {
+    k.n[i] = L.n[i];
+    k.nb[i] = K.nb[i];
+    k.E[i] = K.E[i];
+  }
+  k.fs = L.fs;
+  k.vs = L.vs;
+  k.ns = K.ns;
+  k.box = K.box;
+  k.ls = K.ls;
+  k.nreg = K.nreg;
+  k.val = (const cx<T>*)K.val[a][p].p;
+  k.inv = (const T*)K.inv[a][p].p;
+  k.tab = (const int*)K.tab[a].p;
+  k.dl = (const int*)K.dl[a].p;
+  k.gptr = (const int*)K.gptr[a].p;
+  k.gent = (const int*)K.gent[a].p;
+  k.omega = (T)(H->d.coarse_damping > 0 ? H->d.coarse_damping : 0.8);
+  return k;
+}
+
+// z = `sweeps` hybrid Kaczmarz sweeps from zero on S z_u = v_u (z_p = 0)
+template <typename T>
+static int kacz_apply(elh_handle* H, bool adj, const void* v, void* z, int nrhs, int sweeps) {
+  const LevelData& L = H->lv[H->nlev - 1];
+  KaczData& K = H->kz;
+  if (ensure(K.scr, (size_t)nrhs * K.nreg * K.ls * sizeof(cx<T>))) return ELH_ERR_OOM;
+  const KaczArgs<T> k = kacz_args<T>(H, adj);
+  CHK(launch_zero(z, (int64_t)nrhs * L.vs * (int64_t)sizeof(cx<T>), H->st));
+  for (int s = 0; s < sweeps; ++s) {
+    CHK(launch_kacz_sweep<T>(k, v, s == 0 ? nullptr : z, K.scr.p, nrhs, H->st));
+    CHK(launch_kacz_avg<T>(k, K.scr.p, z, nrhs, H->st));
+  }
+  return 0;
+}
+
+// x = FGMRES on the Schur complement (preconditioned by kacz_apply), then
+// the pressure by back-substitution
+template <typename T>
+static int kacz_coarse_solve(elh_handle* H, bool adj, const void* b, void* x, int nrhs) {
+  const int l = H->nlev - 1;
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const elh_desc& d = H->d;
+  const LevelData& L = H->lv[l];
+  KaczData& K = H->kz;
+  const size_t vb = (size_t)nrhs * L.vs * sizeof(cx<T>);
+  if (ensure(K.t, vb) || ensure(K.y, vb) || ensure(K.bs, vb)) return ELH_ERR_OOM;
+  const KaczArgs<T> k = kacz_args<T>(H, adj);
+  const void* app = K.app[prec].p;
+  hipStream_t st = H->st;
+  // Schur right-hand side b_u - A_up A_pp^-1 b_p (p entries zero)
+  CHK(launch_kacz_elem<T>(0, d.dim, L.fs, L.vs, nrhs, app, adj ? 1 : 0, b, nullptr, K.t.p, st));
+  CHK(op_apply<T>(H, l, true, adj, K.t.p, nullptr, K.y.p, nrhs));
+  CHK(launch_kacz_elem<T>(1, d.dim, L.fs, L.vs, nrhs, app, adj ? 1 : 0, b, K.y.p, K.bs.p, st));
+  auto AZ = [&](const void* zi, void* wo) { return launch_kacz_spmv<T>(k, zi, nullptr, wo, nrhs, st); };
+  auto AR = [&](const void* xi, const void* bi, void* ro) { return launch_kacz_spmv<T>(k, xi, bi, ro, nrhs, st); };
+  auto M = [&](const void* v, void* z) { return kacz_apply<T>(H, adj, v, z, nrhs, d.coarse_sweeps); };
+  if (d.coarse_rtol <= 0) {
+    CHK(gmres_device<T>(H, H->kin[prec], L.vs, nrhs, AZ, AR, M, K.bs.p, x, d.coarse_restart, d.coarse_maxit));
+  } else {
+    GmresStats gs;
+    int rc = gmres<T, T>(H, H->kin[prec], L.vs, nrhs, AZ, AR, M, K.bs.p, x, d.coarse_restart, d.coarse_maxit,
+                         d.coarse_rtol, gs, nullptr);
+    if (rc < 0) return rc;
+  }
+  // p = A_pp^-1 (b_p - A_pu u); the pressure entries of x are zero here
+  CHK(op_apply<T>(H, l, true, adj, x, nullptr, K.y.p, nrhs));
+  CHK(launch_kacz_elem<T>(2, d.dim, L.fs, L.vs, nrhs, app, adj ? 1 : 0, b, K.y.p, x, st));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // coarsest solve and cycle
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -918,6 +1278,10 @@ static int coarse_solve(elh_handle* H, bool adj, const void* b, void* x, int nrh
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const elh_desc& d = H->d;
   if (d.coarse_mode == ELH_COARSE_RELAX) return op_sweeps_from_zero<T>(H, l, adj, b, x, nrhs, d.coarse_sweeps);
+  if (d.coarse_mode == ELH_COARSE_KACZMARZ) {
+    if (nrhs > MAXRHS_KRYLOV) return fail(ELH_ERR_ARG, "at most %d right-hand sides with the Kaczmarz coarse solve", MAXRHS_KRYLOV);
+    return kacz_coarse_solve<T>(H, adj, b, x, nrhs);
+  }
   if (d.coarse_mode == ELH_COARSE_DENSE) {
     // Q = inv(H_s^T):  H_s^{-1} b = Q^T b,  (H_s^H)^{-1} b = conj(Q) b
     const void* Q = prec == 0 ? H->dq64.p : H->dq32.p;
@@ -1054,7 +1418,8 @@ static int run_graph(elh_handle* H, int prec, int adj, int nrhs, const void* in,
 }
 
 static bool graphs_ok(const elh_handle* H) {
-  return H->use_graphs && !(H->d.coarse_mode == ELH_COARSE_KRYLOV && H->d.coarse_rtol > 0);
+  return H->use_graphs && !((H->d.coarse_mode == ELH_COARSE_KRYLOV || H->d.coarse_mode == ELH_COARSE_KACZMARZ) &&
+                             H->d.coarse_rtol > 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1142,6 +1507,19 @@ extern "C" int elh_coarse_solve(elh_handle* H, int flags, int dtype, int nrhs, c
   bool adj = flags & ELH_ADJOINT;
   if (dtype == ELH_C128) CHK(coarse_solve<double>(H, adj, b, x, nrhs));
   else CHK(coarse_solve<float>(H, adj, b, x, nrhs));
+  return 0;
+}
+
+extern "C" int elh_kaczmarz(elh_handle* H, int flags, int dtype, int nrhs, int sweeps, const void* b, void* x) {
+  int rc = check_common(H, H ? H->nlev - 1 : 0, dtype, nrhs);
+  if (rc) return rc;
+  if (H->d.coarse_mode != ELH_COARSE_KACZMARZ) return fail(ELH_ERR_ARG, "handle was not created with ELH_COARSE_KACZMARZ");
+  if (!b || !x || b == x) return fail(ELH_ERR_ARG, "b and x must be distinct non-NULL pointers");
+  if (sweeps < 1) return fail(ELH_ERR_ARG, "sweeps must be >= 1");
+  if (nrhs > MAXRHS_KRYLOV) return fail(ELH_ERR_ARG, "at most %d right-hand sides", MAXRHS_KRYLOV);
+  const bool adj = flags & ELH_ADJOINT;
+  if (dtype == ELH_C128) CHK(kacz_apply<double>(H, adj, b, x, nrhs, sweeps));
+  else CHK(kacz_apply<float>(H, adj, b, x, nrhs, sweeps));
   return 0;
 }
 

@@ -67,6 +67,36 @@ int launch_dense_mv(int64_t N, const void* Q, int transposed, int cj, const void
                     hipStream_t st);
 int launch_gradient(const LevelArgs<double>& L, int dim, int nrhs, const void* u, const void* v, double* gl,
                     double* gm, double* gr, hipStream_t st);
+// Hybrid Kaczmarz on the Schur complement of the pressure at the coarsest
+// level (rows of S in a fixed per-field slot pattern, built on the host).
+constexpr size_t KACZ_MAX_LDS = 65536;  // private copy of one sub-region
+template <typename T> struct KaczArgs {
+  int dim;
+  int n[3];
+  int64_t fs, vs;    // cells per field, entries per vector
+  int ns;            // slots per row
+  int box;           // sub-region edge in cells
+  int nb[3];         // sub-regions per axis (1 beyond dim)
+  int E[3];          // private-copy extent per axis: box + 4 (1 beyond dim)
+  int ls;            // private-copy entries: dim * E[0]*E[1]*E[2]
+  int nreg;          // sub-regions
+  const cx<T>* val;  // [dim*fs][ns] row entries (zero where the column is not an unknown)
+  const T* inv;      // [dim*fs] 1/||row||^2, 0 for rows that are not unknowns
+  const int* tab;    // [dim][ns][4] column field and x_1, x_2, x_3 offsets of each slot
+  const int* dl;     // [dim][ns] the slot's offset inside the private copy
+  const int* gptr;   // [dim*fs + 1] gather list of each unknown: entries gptr[j]..gptr[j+1]-1
+  const int* gent;   // [entries][2] (sub-region, private-copy index)
+  T omega;           // relaxation
+};
+template <typename T>
+int launch_kacz_sweep(const KaczArgs<T>& K, const void* b, const void* xin, void* scr, int nrhs, hipStream_t st);
+template <typename T>
+int launch_kacz_avg(const KaczArgs<T>& K, const void* scr, void* x, int nrhs, hipStream_t st);
+template <typename T>
+int launch_kacz_spmv(const KaczArgs<T>& K, const void* x, const void* b, void* y, int nrhs, hipStream_t st);
+template <typename T>
+int launch_kacz_elem(int mode, int dim, int64_t fs, int64_t vs, int nrhs, const void* app, int cj, const void* b,
+                     const void* y, void* out, hipStream_t st);
 int launch_gm_start(int nrhs, const double* nrm2, double* st, double* scale, hipStream_t s);
 int launch_gm_hcol(int nrhs, int j, const double* dots, double* st, double* coef, hipStream_t s);
 int launch_gm_rotate(int nrhs, int j, const double* nrm2, double* st, double* scale, hipStream_t s);

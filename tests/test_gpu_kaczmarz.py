@@ -1,0 +1,138 @@
+"""GPU parity of the paper's coarsest-grid solver (Section 3.2; parameters
+of Section 5.3): hybrid Kaczmarz sweeps on the Schur complement of the
+pressure, the FGMRES solve they precondition, and a cycle that uses it.
+
+Inputs come from the seeded generators in `synthetic`; expected values from
+`oracle` only.  Float64: the sweeps are chains of row projections whose dot
+products the GPU sums in a different order, so agreement is at rounding
+level (1e-11 relative); the FGMRES solves use classical Gram-Schmidt on the
+GPU and modified Gram-Schmidt in the oracle (1e-9).  Float32: the sweeps in
+single precision against the float64 oracle (3e-5 per sweep pass).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import grid as G
+from oracle import operator as O
+from oracle import cycle as C
+from oracle import kaczmarz as K
+from synthetic import make_media, random_field, omega_for_ppw
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(shape, box, levels=1, alpha=0.5, seed=6, sweeps=10, maxit=25, rtol=0.1, cycle="V",
+           precond=torch.complex128):
+    from paper_2307_03242_amd import Problem
+    m = make_media(shape, seed)
+    om = omega_for_ppw(m["vs"].min(), 1.0, 10)
+    abl = 0.25 * min(shape)
+    prob = Problem(torch.from_numpy(m["lam"]), torch.from_numpy(m["mu"]), torch.from_numpy(m["rho"]),
+                   h=1.0, omega=om, gamma=0.01, alpha=alpha, beta=2 / 3, abl_width=abl, abl_amp=2.0,
+                   levels=levels, damping=(0.55, 0.35, 0.25), coarse_mode="kaczmarz",
+                   coarse_sweeps=sweeps, coarse_restart=5, coarse_maxit=maxit, coarse_rtol=rtol,
+                   coarse_damping=0.0, kacz_box=box, cycle=cycle, precond_dtype=precond)
+    lv = G.Level(tuple(reversed(shape)), 1.0, om, 0.01, 2 / 3, m["lam"], m["mu"], m["rho"],
+                 abl_width=abl, abl_amp=2.0)
+    return prob, lv
+
+
+def _dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().to(torch.complex128).numpy()
+
+
+def _relerr(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def _op(lv, alpha, adjoint):
+    A = O.assemble(lv, shift=alpha)
+    return A.conj().T.tocsr() if adjoint else A
+
+
+def _oracle_sweeps(lv, A, b, box, sweeps, adjoint):
+    S = K.schur_blocks(lv, A)[0]
+    kz = K.HybridKaczmarz(lv, S, box=box, omega=0.8, adjoint=adjoint)
+    nu = S.shape[0]
+    out = []
+    for s in range(b.shape[0]):
+        xu = kz.apply(G.pack(lv, b[s])[:nu], sweeps)
+        out.append(G.unpack(lv, np.concatenate([xu, np.zeros(G.pack(lv, b[s]).size - nu)])))
+    return np.stack(out)
+
+
+# (numpy shape, box): ragged boxes along every axis, several sub-regions
+CASES = [((7, 6, 9), 2), ((9, 8, 10), 4), ((6, 5, 7), 3), ((13, 10), 4), ((11, 14), 5)]
+
+
+@pytest.mark.parametrize("shape,box", CASES)
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_hybrid_kaczmarz_sweeps_f64(shape, box, adjoint):
+    prob, lv = _setup(shape, box)
+    b = random_field(shape, 31, nrhs=2)
+    got = _host(prob.kaczmarz(_dev(b), 3, adjoint=adjoint))
+    ref = _oracle_sweeps(lv, _op(lv, 0.5, adjoint), b, box, 3, adjoint)
+    assert _relerr(got, ref) <= 1e-11
+    assert np.all(got[:, -1] == 0)  # pressure entries
+
+
+@pytest.mark.parametrize("shape,box", [((7, 6, 9), 2), ((13, 10), 4)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_hybrid_kaczmarz_sweeps_f32(shape, box, adjoint):
+    prob, lv = _setup(shape, box)
+    b = random_field(shape, 32, nrhs=1)
+    got = _host(prob.kaczmarz(_dev(b, torch.complex64), 2, adjoint=adjoint))
+    ref = _oracle_sweeps(lv, _op(lv, 0.5, adjoint), b.astype(np.complex64).astype(np.complex128), box, 2,
+                         adjoint)
+    assert _relerr(got, ref) <= 3e-5
+
+
+@pytest.mark.parametrize("shape,box", [((7, 6, 9), 2), ((8, 8, 8), 4), ((13, 10), 4)])
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("rtol,maxit", [(0.1, 25), (0.0, 7)])
+def test_schur_kaczmarz_coarse_solve_f64(shape, box, adjoint, rtol, maxit):
+    """the whole coarsest solve: elimination of p, FGMRES(5) preconditioned
+    by 10 sweeps, residual-drop stop (host-synchronised) or fixed budget
+    (device-resident), back-substitution of p"""
+    prob, lv = _setup(shape, box, rtol=rtol, maxit=maxit)
+    b = random_field(shape, 33, nrhs=2)
+    got = _host(prob.coarse_solve(_dev(b), adjoint=adjoint))
+    A = _op(lv, 0.5, adjoint)
+    sol = K.SchurKaczmarzSolver(lv, A, box=box, omega=0.8, sweeps=10, restart=5, rtol=rtol, maxit=maxit,
+                                adjoint=adjoint)
+    ref = np.stack([G.unpack(lv, sol.solve(G.pack(lv, b[s]))) for s in range(2)])
+    assert _relerr(got, ref) <= 1e-9
+
+
+def test_vcycle_with_kaczmarz_coarse_solve_f64():
+    """two-level V-cycle whose coarsest solve is the Schur/Kaczmarz solver
+    (fixed budget, so the cycle is graph-captured) against the oracle's"""
+    shape = (8, 12, 16)
+    prob, lv = _setup(shape, 2, levels=2, rtol=0.0, maxit=6, alpha=0.3)
+    cp = C.CycleParams(levels=2, alpha=0.3, damping=(0.55, 0.35, 0.25), coarse="kaczmarz", coarse_sweeps=10,
+                       coarse_restart=5, coarse_maxit=6, coarse_rtol=0.0, kacz_box=2)
+    hier = C.Hierarchy(lv, cp)
+    b = random_field(shape, 34, nrhs=2)
+    ref = np.stack([hier.vcycle_storage(b[s]) for s in range(2)])
+    for _ in range(3):  # eager, captured, replayed
+        x = _host(prob.vcycle(_dev(b)))
+        assert _relerr(x, ref) <= 1e-9
+
+
+def test_mixed_precision_solve_with_kaczmarz_coarse_solve():
+    """the paper's 3D configuration: float32 K-cycle whose coarsest solve is
+    the Schur/Kaczmarz solver (residual drop 0.1, <= 250 sweeps) inside the
+    float64 FGMRES; converges to 1e-6 in true residual"""
+    shape = (32, 32, 32)
+    prob, lv = _setup(shape, 4, levels=3, cycle="K", precond=torch.complex64)
+    q = torch.zeros((1, 4) + shape, dtype=torch.complex128)
+    q[0, 2, 16, 16, 16] = 1.0
+    u, info, code = prob.solve(q.cuda(), rtol=1e-6, maxit=80)
+    assert code == 0 and info[0]["status"] == 0 and info[0]["relres"] <= 1e-6
+    r = prob.residual(q.cuda(), u)
+    assert (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(q)).item() <= 1e-6 * (1 + 1e-6)
