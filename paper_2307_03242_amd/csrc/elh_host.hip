@@ -1044,8 +1044,10 @@ static int build_kaczmarz(elh_handle* H) {
         dl[(size_t)k * ns + q] = (int)(t[0] * ee + (t[3] * K.E[1] + t[2]) * K.E[0] + t[1]);
       }
     // rows
-    std::vector<double> v64((size_t)nu * ns * 2, 0.0), i64(nu, 0.0);
-    std::vector<float> v32((size_t)nu * ns * 2, 0.0f), i32(nu, 0.0f);
+    // 128 zero slots of padding after the last row: the sweep's lanes load
+    // slots lane and lane + 64 of every row unconditionally
+    std::vector<double> v64(((size_t)nu * ns + 128) * 2, 0.0), i64(nu, 0.0);
+    std::vector<float> v32(((size_t)nu * ns + 128) * 2, 0.0f), i32(nu, 0.0f);
     for (int k = 0; k < dim; ++k)
       for (int z = 0; z < n2; ++z)
         for (int y = 0; y < n1; ++y)

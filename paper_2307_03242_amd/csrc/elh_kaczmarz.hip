@@ -13,8 +13,9 @@
 //   k_kacz_sweep  one wavefront per (sub-region, rhs): the private copy of
 //                 the sub-region's neighbourhood lives in LDS; rows are taken
 //                 in ascending global order; lanes hold the row's slots, one
-//                 butterfly sum gives a_i . x and every lane applies its
-//                 slots' share of the projection;
+//                 DPP sum gives a_i . x (wave-uniform) and every lane applies
+//                 its slots' share of the projection; the next row's entries
+//                 are loaded during the current projection;
 //   k_kacz_avg    one thread per displacement unknown: mean over its
 //                 gather list (sub-region, LDS slot), fixed order;
 //   k_kacz_spmv   one wavefront per row: y = S x or y = b - S x (pressure
@@ -31,6 +32,58 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
   return v;
+}
+
+// DPP move with row mask RM; lanes of disabled rows read zero.
+template <int CTRL, int RM> __device__ __forceinline__ float dpp0(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, RM, 0xf, false));
+}
+template <int CTRL, int RM> __device__ __forceinline__ double dpp0(double v) {
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, RM, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over the 64 lanes, wave-uniform result: pairs and quads (quad
+// permutes), rows of 16 (row rotates by 4 and 8), then the row broadcasts
+// carry rows 0+1 and 2+3 and finally all four rows into lane 63.
+template <typename T> __device__ __forceinline__ T wave_total(T v) {
+  v += dpp0<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp0<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp0<0x124, 0xf>(v);  // row_ror:4
+  v += dpp0<0x128, 0xf>(v);  // row_ror:8
+  v += dpp0<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp0<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+  return lane63(v);
+}
+
+// Raw buffer resource and vector loads through it (wave-uniform addresses
+// stay in the vector memory pipeline, counted with the other loads).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t kacz_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                           (int)(bytes > 0x7fffffffll ? 0x7fffffffll : bytes), 0x00020000);
+}
+template <typename V> __device__ __forceinline__ V kacz_load(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ float kacz_load<float>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double kacz_load<double>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ cx<float> kacz_load<cx<float>>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ cx<double> kacz_load<cx<double>>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
 template <typename T>
@@ -66,32 +119,77 @@ __global__ void __launch_bounds__(64) k_kacz_sweep(KaczArgs<T> K, const cx<T>* _
     X[q] = v;
   }
   __syncthreads();
-  const cx<T>* bs = b + vb;
   const int q0 = lane, q1 = lane + 64;
-  for (int k = 0; k < K.dim; ++k) {
-    const int* dlk = K.dl + k * K.ns;
-    const int d0 = q0 < K.ns ? dlk[q0] : 0, d1 = q1 < K.ns ? dlk[q1] : 0;
-    for (int z = c0[2]; z < c1[2]; ++z)
-      for (int y = c0[1]; y < c1[1]; ++y)
-        for (int x = c0[0]; x < c1[0]; ++x) {
-          const int c[3] = {x, y, z};
-          if (c[k] == 0) continue;  // boundary face: not an unknown
-          const int64_t row = k * K.fs + ((int64_t)z * K.n[1] + y) * K.n[0] + x;
-          const T inv = K.inv[row];
-          if (inv == T(0)) continue;
-          const int lb = ((z - lo[2]) * K.E[1] + (y - lo[1])) * K.E[0] + (x - lo[0]);
-          const cx<T>* vr = K.val + row * K.ns;
-          const cx<T> a0 = q0 < K.ns ? vr[q0] : czero<T>();
-          const cx<T> a1 = q1 < K.ns ? vr[q1] : czero<T>();
-          const int l0 = lb + d0, l1 = lb + d1;
-          cx<T> acc = a0 * X[l0];
-          if (q1 < K.ns) acc += a1 * X[l1];
-          const T dre = wave_sum(acc.re), dim_ = wave_sum(acc.im);
-          const cx<T> res = bs[row] - mk(dre, dim_);
-          const cx<T> coef = (K.omega * inv) * res;
-          if (q0 < K.ns) X[l0] += coef * conj(a0);
-          if (q1 < K.ns) X[l1] += coef * conj(a1);
-        }
+  const bool has1 = q1 < K.ns;
+  // rows of the sub-region in ascending global order: an odometer over
+  // (field, x_3, x_2, x_1) of the box.  Boundary faces (not unknowns) hold
+  // zero entries and 1/||a||^2 = 0, so their projection changes nothing and
+  // every box position is taken in turn.  Four register sets form a ring:
+  // the entries, 1/||a||^2 and b_i of the rows three ahead are in flight
+  // while a row is projected.  Every lane loads unconditionally (the row
+  // table carries 128 zero slots of padding at its end) and surplus slots
+  // are multiplied by zero, so the loop is straight-line.
+  const T m0 = q0 < K.ns ? T(1) : T(0), m1 = has1 ? T(1) : T(0);
+  int dls[3][2];
+  for (int k = 0; k < 3; ++k) {
+    dls[k][0] = k < K.dim && q0 < K.ns ? K.dl[k * K.ns + q0] : 0;
+    dls[k][1] = k < K.dim && has1 ? K.dl[k * K.ns + q1] : 0;
+  }
+  const int w0 = c1[0] - c0[0], w1 = c1[1] - c0[1], w2 = c1[2] - c0[2];
+  const int nt = K.dim * w0 * w1 * w2;
+  const __amdgpu_buffer_rsrc_t rb = kacz_rsrc(b + vb, K.vs * (int64_t)sizeof(cx<T>));
+  const __amdgpu_buffer_rsrc_t ri = kacz_rsrc(K.inv, (int64_t)K.dim * K.fs * (int64_t)sizeof(T));
+  struct Row {
+    int c[3], k;
+    cx<T> a0, a1, bi;
+    T inv;
+  };
+  auto step = [&](Row& r) {
+    if (++r.c[0] < c1[0]) return;
+    r.c[0] = c0[0];
+    if (++r.c[1] < c1[1]) return;
+    r.c[1] = c0[1];
+    if (++r.c[2] < c1[2]) return;
+    r.c[2] = c0[2];
+    ++r.k;
+  };
+  // past the last row the odometer's field index runs to dim: fetch() clamps
+  // it, and those rows are never projected
+  auto fetch = [&](Row& r) {
+    const int row = min(r.k, K.dim - 1) * (int)K.fs + (r.c[2] * K.n[1] + r.c[1]) * K.n[0] + r.c[0];
+    const cx<T>* vr = K.val + (int64_t)row * K.ns;
+    const cx<T> v0 = vr[q0], v1 = vr[q1];
+    r.a0 = mk(v0.re * m0, v0.im * m0);
+    r.a1 = mk(v1.re * m1, v1.im * m1);
+    r.bi = kacz_load<cx<T>>(rb, row * (int)sizeof(cx<T>));
+    r.inv = kacz_load<T>(ri, row * (int)sizeof(T));
+  };
+  auto project = [&](const Row& r) {
+    const int lb = ((r.c[2] - lo[2]) * K.E[1] + (r.c[1] - lo[1])) * K.E[0] + (r.c[0] - lo[0]);
+    const int l0 = lb + dls[r.k][0], l1 = lb + dls[r.k][1];
+    const cx<T> acc = r.a0 * X[l0] + r.a1 * X[l1];
+    const T dre = wave_total(acc.re), dim_ = wave_total(acc.im);
+    const cx<T> coef = (K.omega * r.inv) * (r.bi - mk(dre, dim_));
+    // surplus lanes point at the row's own slot: they must not store
+    if (q0 < K.ns) X[l0] += coef * conj(r.a0);
+    if (has1) X[l1] += coef * conj(r.a1);
+  };
+  Row R[4];
+  R[0].c[0] = c0[0]; R[0].c[1] = c0[1]; R[0].c[2] = c0[2]; R[0].k = 0;
+#pragma unroll
+  for (int j = 1; j < 4; ++j) {
+    R[j].c[0] = R[j - 1].c[0]; R[j].c[1] = R[j - 1].c[1]; R[j].c[2] = R[j - 1].c[2]; R[j].k = R[j - 1].k;
+    step(R[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) fetch(R[j]);
+  for (int i = 0; i < nt; i += 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (i + j < nt) project(R[j]);
+      step(R[j]); step(R[j]); step(R[j]); step(R[j]);
+      fetch(R[j]);
+    }
   }
   __syncthreads();
   cx<T>* out = scr + ((int64_t)s * K.nreg + r) * K.ls;
