@@ -35,7 +35,7 @@ RESID_BYTES_F32 = 108      # residual b - H_s x in complex64: x, b, y (32 B each
 # by what the same counter reads for a 1 GiB device copy: x2.0 for FETCH_SIZE,
 # x1.0 for WRITE_SIZE): 1.484 GB read + 0.559 GB written.  Set to None when
 # the kernel changes until the passes are repeated.
-RESID_TRAFFIC_BYTES = 2.042e9
+RESID_TRAFFIC_BYTES = 2.108e9
 
 
 def parse():
@@ -99,9 +99,9 @@ def cpu_baseline(args, gpu_iters, cfg):
     per_iter_cell = dt / info["iters"] / (n ** 3)
     t_solve = per_iter_cell * (args.n ** 3) * gpu_iters
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d outer FGMRES(5)+V-cycle iterations of the float64 oracle on a %d^3 grid "
+            "sample": "%d outer FGMRES(5)+%s-cycle iterations of the float64 oracle on a %d^3 grid "
                       "(same media recipe, %.1f s), scaled per cell to %d^3 and to the GPU's %d iterations"
-                      % (info["iters"], n, dt, args.n, gpu_iters)}
+                      % (info["iters"], args.cycle, n, dt, args.n, gpu_iters)}
 
 
 def solver_cfg(args, omega, levels=None):
@@ -214,6 +214,46 @@ def extras(args):
     phi.backward()
     torch.cuda.synchronize()
     tg = time.perf_counter() - t0
+    # the paper's coarsest solver (Section 3.2: p eliminated, FGMRES(5) on the
+    # Schur complement preconditioned by 10 hybrid Kaczmarz sweeps with
+    # relaxation 0.8, to a residual drop of 0.1 with at most 250 sweeps) in
+    # place of the default coarsest solve, same --n^3 problem and K-cycle
+    n = args.n
+    shape = (n, n, n)
+    mk_, medk = media(shape, args.seed)
+    om = omega_for_ppw(mk_["vs"].min(), 1.0, 10)
+    qk = torch.from_numpy(point_source(shape)[None]).cuda()
+    kz = {"workload": "%d^3, seed %d, 1 point source, float32 %d-level %s-cycle; coarsest solve: Schur complement "
+                      "FGMRES(5), 10 hybrid Kaczmarz sweeps per step (relaxation 0.8), residual drop 0.1, "
+                      "<= 250 sweeps" % (n, args.seed, args.levels, args.cycle)}
+    for box in (2, 4):
+        cfg = solver_cfg(args, om)
+        cfg.update(coarse_mode="kaczmarz", coarse_sweeps=10, coarse_restart=5, coarse_maxit=25, coarse_rtol=0.1,
+                   coarse_damping=0.8)
+        pk = Problem(*medk, precond_dtype=torch.complex64, kacz_box=box, **cfg)
+        cs, _ = pk.level_shape(args.levels - 1)
+        bc = torch.ones((1, 4) + tuple(cs), dtype=torch.complex64, device="cuda")
+        pk.kaczmarz(bc, 10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            pk.kaczmarz(bc, 10)
+        e1.record()
+        e1.synchronize()
+        pk.solve(qk, rtol=args.rtol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, code = pk.solve(qk, rtol=args.rtol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        tk = time.perf_counter() - t0
+        kz["box_%d" % box] = {"solves_per_s": 1.0 / tk, "iters": info[0]["iters"], "code": code,
+                              "coarsest": "%dx%dx%d" % tuple(reversed(cs)),
+                              "ms_per_10_sweeps": e0.elapsed_time(e1) / 10,
+                              "precond_ms": info[0]["t_precond_ms"]}
+        del pk
+        torch.cuda.empty_cache()
+    out["paper_coarsest_solver"] = kz
+
     out["fwi_gradient"] = {
         "workload": "128^3, true medium seed 500, start = true with an 8%% central Gaussian anomaly, 8 sources, "
                     "receivers on the plane at depth 18; forward + adjoint solves to %.0e + gradient kernel" % args.rtol,

@@ -14,12 +14,12 @@ pytestmark = pytest.mark.gpu
 SHAPE = (10, 12, 70)  # (n_3, n_2, n_1): 8400 cells, two x_1 segments
 
 
-def _problem(env):
+def _problem(env, shape=SHAPE):
     from paper_2307_03242_amd import Problem
     old = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
-        m = make_media(SHAPE, 7)
+        m = make_media(shape, 7)
         return Problem(torch.from_numpy(m["lam"]), torch.from_numpy(m["mu"]), torch.from_numpy(m["rho"]),
                        h=1.0, omega=omega_for_ppw(m["vs"].min(), 1.0, 10), gamma=0.01, alpha=0.3,
                        abl_width=3.0, abl_amp=2.0, levels=1)
@@ -64,3 +64,28 @@ def test_tune_cache_persists_choices(tmp_path):
     b = _problem({"ELH_TUNE": "1", "ELH_TUNE_CACHE": path})
     assert b.stencil_choice(0, torch.complex128) == c  # loaded at creation, before any call
     assert np.array_equal(b.apply(x).cpu().numpy(), a.apply(x).cpu().numpy())
+
+
+@pytest.mark.parametrize("shape", [SHAPE, (17, 9, 130)])
+def test_every_chunk_length_gives_the_same_bits(shape):
+    """forced x_3 chunks of 1..16 planes, odd and even, ragged last chunk:
+    forward and adjoint apply and residual, both precisions, bitwise equal"""
+    x = torch.from_numpy(random_field(shape, 8, nrhs=2)).cuda()
+    b = torch.from_numpy(random_field(shape, 9, nrhs=2)).cuda()
+    outs = {}
+    for zc in (None, 1, 2, 3, 4, 5, 7, 16):
+        env = {"ELH_TUNE": "0"}
+        if zc is not None:
+            env["ELH_ZCHUNK"] = str(-zc)
+        p = _problem(env, shape)
+        res = []
+        for dt in (torch.complex128, torch.complex64):
+            for adj in (False, True):
+                res.append(p.apply(x.to(dt), adjoint=adj))
+                res.append(p.residual(b.to(dt), x.to(dt), shifted=True, adjoint=adj))
+        torch.cuda.synchronize()
+        outs[zc] = [r.cpu() for r in res]
+        p.close()
+    for zc, res in outs.items():
+        for r, ref in zip(res, outs[None]):
+            assert torch.equal(r, ref), zc
