@@ -158,6 +158,13 @@ int elh_destroy(elh_handle* h);
 int elh_apply(elh_handle* h, int level, int flags, int dtype, int nrhs,
               const void* x, void* y);
 
+/* y = H x on level 0 with x in complex64 and float64 arithmetic and output:
+ * the outer operator of the mixed-precision solve (Section 5.3), applied to
+ * the float32 preconditioned vectors.  x: (nrhs, dim+1, n_d..n_1) complex64,
+ * y: same shape complex128, distinct buffers.  flags: ELH_ADJOINT (H^H);
+ * ELH_SHIFTED is rejected (ELH_ERR_ARG).  Errors as elh_apply. */
+int elh_apply_f32in(elh_handle* h, int flags, int nrhs, const void* x, void* y);
+
 /* r = b - H x  (same operator selection as elh_apply); r may alias b. */
 int elh_residual(elh_handle* h, int level, int flags, int dtype, int nrhs,
                  const void* b, const void* x, void* r);

@@ -13,7 +13,7 @@ ELH_COARSE_KRYLOV, ELH_COARSE_DENSE, ELH_COARSE_RELAX, ELH_COARSE_KACZMARZ = 0, 
 
 EXPORTED = [
     "elh_create", "elh_set_media", "elh_destroy", "elh_apply", "elh_residual",
-    "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_coarse_solve", "elh_kaczmarz",
+    "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_coarse_solve", "elh_kaczmarz", "elh_apply_f32in",
     "elh_vcycle", "elh_solve", "elh_solve_adjoint", "elh_solve_batch", "elh_gradient",
     "elh_level_info", "elh_stencil_choice", "elh_status_string", "elh_last_error",
 ]
@@ -73,6 +73,7 @@ def load():
         "elh_relax": [H, ip, ip, ip, ip, ip, vp, vp],
         "elh_coarse_solve": [H, ip, ip, ip, vp, vp],
         "elh_kaczmarz": [H, ip, ip, ip, ip, vp, vp],
+        "elh_apply_f32in": [H, ip, ip, vp, vp],
         "elh_vcycle": [H, ip, ip, ip, vp, vp],
         "elh_solve": [H, ip, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
         "elh_solve_adjoint": [H, ip, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],

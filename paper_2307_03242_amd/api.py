@@ -164,6 +164,18 @@ class Problem:
                                    _ptr(x), _ptr(y)))
         return y
 
+    def apply_f32_input(self, x, adjoint=False, out=None):
+        """y = H x (level 0, complex128) from complex64 x with float64
+        arithmetic: the outer operator of the mixed-precision solve."""
+        if x.dtype != torch.complex64:
+            raise TypeError("x must be complex64")
+        nrhs = self._vec(x, 0)
+        y = torch.empty(x.shape, dtype=torch.complex128, device=x.device) if out is None else out
+        if y.dtype != torch.complex128 or y.shape != x.shape or not y.is_contiguous():
+            raise ValueError("out must be a contiguous complex128 tensor of x's shape")
+        L.check(self.lib.elh_apply_f32in(self.handle, self._flags(False, adjoint), nrhs, _ptr(x), _ptr(y)))
+        return y
+
     def residual(self, b, x, level=0, shifted=False, adjoint=False, out=None):
         nrhs = self._vec(x, level)
         self._same(b, x, "b")

@@ -1437,6 +1437,26 @@ extern "C" int elh_apply(elh_handle* H, int level, int flags, int dtype, int nrh
   return 0;
 }
 
+extern "C" int elh_apply_f32in(elh_handle* H, int flags, int nrhs, const void* x, void* y) {
+  int rc = check_common(H, 0, ELH_C128, nrhs);
+  if (rc) return rc;
+  if (!x || !y || x == y) return fail(ELH_ERR_ARG, "x and y must be distinct non-NULL pointers");
+  if (flags & ELH_SHIFTED) return fail(ELH_ERR_ARG, "the outer operator is unshifted");
+  const bool adj = flags & ELH_ADJOINT;
+  const LevelData& L0 = H->lv[0];
+  const bool direct = H->d.dim == 3 && !adj && H->stencil == 0 && L0.fs >= 16 * 16 * 16 &&
+                      L0.fs * 16 <= (int64_t)0x7fffffff;
+  if (direct) {
+    CHK(op_apply_f32in(H, adj, x, y, nrhs));
+    return 0;
+  }
+  // other layouts: widen to float64 first (as the solve does)
+  if (ensure(H->tmpvec, (size_t)nrhs * L0.vs * 16)) return ELH_ERR_OOM;
+  CHK((launch_scale_copy<cx<float>, cx<double>>(nullptr, x, L0.vs, H->tmpvec.p, L0.vs, L0.vs, nrhs, H->st)));
+  CHK(op_apply<double>(H, 0, false, adj, H->tmpvec.p, nullptr, y, nrhs));
+  return 0;
+}
+
 extern "C" int elh_residual(elh_handle* H, int level, int flags, int dtype, int nrhs, const void* b, const void* x,
                             void* r) {
   int rc = check_common(H, level, dtype, nrhs);

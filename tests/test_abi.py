@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "elh.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(elh_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(elh_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_abi():

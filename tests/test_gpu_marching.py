@@ -118,3 +118,15 @@ def test_marching_vcycle_and_adjoint_vcycle(shape):
         ref = hier.vcycle_storage(b[0])
         got = _host(prob.vcycle(_dev(b), adjoint=adjoint))[0]
         assert _maxrel(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_outer_operator_on_float32_input(shape, adjoint):
+    """the mixed solve's outer operator: complex64 input, float64 arithmetic
+    (forward through the march's float32-input variant, adjoint widened)"""
+    prob, lv = _setup(shape)
+    x = random_field(shape, 61, nrhs=2).astype(np.complex64)
+    ref = np.stack([O.apply(lv, x[s].astype(np.complex128), adjoint=adjoint) for s in range(2)])
+    y = _host(prob.apply_f32_input(_dev(x, torch.complex64), adjoint=adjoint))
+    assert _maxrel(y, ref) <= TOL64
