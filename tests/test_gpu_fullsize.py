@@ -84,3 +84,126 @@ def test_mixed_precision_solve_full_size(bench_problem):
     rel = np.linalg.norm(r.ravel()) / np.linalg.norm(q.ravel())
     assert rel <= 1e-6 * (1 + 1e-3)
     assert abs(rel - info[0]["relres"]) <= 1e-9
+
+
+def _solver(m, shape, precond, levels, alpha=0.5, abl=ABL):
+    from paper_2307_03242_amd import Problem
+    om = omega_for_ppw(m["vs"].min(), 1.0, 10)
+    args = dict(h=1.0, omega=om, gamma=0.01, alpha=alpha, beta=2 / 3, abl_width=abl, abl_amp=2.0, levels=levels,
+                nu1=1, nu2=1, cycle="K", damping=(0.6, 0.5, 0.4, 0.4), coarse_mode="krylov", coarse_sweeps=1,
+                coarse_restart=5, coarse_maxit=2, coarse_rtol=0.0)
+    med = [torch.from_numpy(m[k]) for k in ("lam", "mu", "rho")]
+    prob = Problem(*med, precond_dtype=precond, **args)
+    lv = G.Level(tuple(reversed(shape)), 1.0, om, 0.01, 2 / 3, m["lam"], m["mu"], m["rho"],
+                 abl_width=abl, abl_amp=2.0)
+    return prob, lv
+
+
+def _oracle_relres(lv, q, u):
+    r = q - O.apply(lv, u)
+    return np.linalg.norm(r.ravel()) / np.linalg.norm(q.ravel())
+
+
+def test_fp64_solve_128_full_size():
+    """plain float64 solve at 128^3 (seed 2, one centred source) to 1e-8:
+    true residual recomputed with the oracle's operator"""
+    shape = (128, 128, 128)
+    prob, lv = _solver(make_media(shape, 2), shape, torch.complex128, levels=3)
+    q = point_source(shape)[None]
+    u, info, code = prob.solve(torch.from_numpy(q).cuda(), rtol=1e-8, maxit=500)
+    assert code == 0
+    rel = _oracle_relres(lv, q[0], u.cpu().numpy()[0])
+    assert rel <= 1e-8 * (1 + 1e-3)
+    prob.close()
+
+
+def test_batched_sources_160_full_size():
+    """32 point sources on 160^3 in one batched mixed-precision solve to
+    1e-6: two sampled sources' true residuals recomputed by the oracle"""
+    from synthetic import lattice_sources
+    shape = (160, 160, 160)
+    prob, lv = _solver(make_media(shape, 4), shape, torch.complex64, levels=4)
+    q = lattice_sources(shape, 4, 8, depth_index=int(ABL) + 2, margin=int(ABL))
+    u, info, code = prob.solve(torch.from_numpy(q).cuda(), rtol=1e-6, maxit=400)
+    assert code == 0 and all(i["status"] == 0 for i in info)
+    un = u.cpu().numpy()
+    for s in (0, 29):
+        assert _oracle_relres(lv, q[s], un[s]) <= 1e-6 * (1 + 1e-3)
+    prob.close()
+
+
+def test_uneven_batch_full_size():
+    """the 12 uneven problems (64^3 .. 192^3, seeds 100-111) solved
+    together: the smallest and largest problems' true residuals recomputed
+    by the oracle"""
+    from paper_2307_03242_amd import Problem
+    sizes = [64, 80, 96, 112, 128, 144, 160, 176, 192, 96, 128, 160]
+    probs, lvs, qs = [], [], []
+    for i, n in enumerate(sizes):
+        sh = (n, n, n)
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            p, lv = _solver(make_media(sh, 100 + i), sh, torch.complex64, levels=4)
+        probs.append(p)
+        lvs.append(lv)
+        qs.append(torch.from_numpy(point_source(sh)[None]).cuda())
+    us, infos, code = Problem.solve_batch(probs, qs, rtol=1e-6, maxit=400)
+    assert code == 0
+    for i in (0, 8):
+        assert _oracle_relres(lvs[i], qs[i].cpu().numpy()[0], us[i].cpu().numpy()[0]) <= 1e-6 * (1 + 1e-3)
+    for p in probs:
+        p.close()
+
+
+def test_fwi_gradient_128_finite_differences():
+    """the FWI-style gradient at 128^3 (true medium seed 500, start = true
+    with an 8 % central Gaussian anomaly, 8 sources at depth 18, receivers
+    on the plane at depth 18): directional derivatives along 20 smooth
+    random directions (seed 502) equal central finite differences to 1e-4.
+
+    Step: the misfit is strongly nonlinear along these directions (a blob of
+    the full medium's size per unit step): the central difference's
+    O(eps^2) error is 1e-3..2e-3 relative at eps = 1e-4 and grows 100-fold
+    per decade of eps, independent of the solve tolerance (1e-12 and 1e-13
+    give the same differences).  eps = 5e-6 puts it near 5e-6; the solves'
+    misfit noise (2.5e-18 between tolerances 1e-12 and 1e-13, against
+    differences of 1e-13 and more) stays below 2e-5."""
+    from paper_2307_03242_amd.autograd import misfit
+    from synthetic import lattice_sources
+    n = 128
+    shape = (n, n, n)
+    mt = make_media(shape, 500)
+    prob, _ = _solver(mt, shape, torch.complex128, levels=3)
+    src = torch.from_numpy(lattice_sources(shape, 2, 4, depth_index=18, margin=int(ABL))).cuda()
+    mask = torch.zeros((4,) + shape, dtype=torch.bool, device="cuda")
+    a = int(ABL)
+    mask[:3, 18, a:-a, a:-a] = True
+    true = [torch.from_numpy(mt[k]).cuda() for k in ("lam", "mu", "rho")]
+    prob.set_media(*true)
+    d_obs, _, code = prob.solve(src, rtol=1e-12, maxit=3000)
+    assert code == 0
+    d_obs = d_obs * mask
+    z, y, x = torch.meshgrid(*[torch.arange(n, dtype=torch.float64, device="cuda") + 0.5] * 3, indexing="ij")
+    blob = 1.0 - 0.08 * torch.exp(-((z - n / 2) ** 2 + (y - n / 2) ** 2 + (x - n / 2) ** 2) / (2 * 12.0 ** 2))
+    base = [t * blob for t in true]
+    params = [b.clone().requires_grad_(True) for b in base]
+    phi = misfit(prob, *params, src, mask, d_obs, rtol=1e-12, maxit=3000)
+    phi.backward()
+    grads = [p.grad.clone() for p in params]
+    rng = np.random.default_rng(502)
+    worst = 0.0
+    for trial in range(20):
+        dirs = []
+        for b in base:
+            c = rng.uniform(0.3 * n, 0.7 * n, 3)
+            d = torch.exp(-((z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2) / (2 * (n / 10.0) ** 2))
+            dirs.append(d * float(rng.uniform(-1, 1)) * float(b.abs().max()))
+        eps = 5e-6
+        with torch.no_grad():
+            pp = misfit(prob, *[b + eps * d for b, d in zip(base, dirs)], src, mask, d_obs, rtol=1e-12, maxit=3000)
+            pm = misfit(prob, *[b - eps * d for b, d in zip(base, dirs)], src, mask, d_obs, rtol=1e-12, maxit=3000)
+        fd = (pp - pm).item() / (2 * eps)
+        an = sum(float((g * d).sum()) for g, d in zip(grads, dirs))
+        worst = max(worst, abs(fd - an) / abs(an))
+    assert worst <= 1e-4, worst
+    prob.close()
