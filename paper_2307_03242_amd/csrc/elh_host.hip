@@ -577,6 +577,8 @@ static double level_damping(const elh_handle* H, int l) {
 
 // one colour of red-black Vanka; x_is_zero lets the residual be b itself
 template <typename T>
+// x_is_zero: the iterate is zero and x holds nothing yet (the residual is b;
+// in 3D the half-sweep writes every entry of x, in 2D x is cleared first)
 static int op_relax(elh_handle* H, int l, bool adj, int colour, const void* b, void* x, int nrhs, bool x_is_zero) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   LevelData& L = H->lv[l];
@@ -584,14 +586,15 @@ static int op_relax(elh_handle* H, int l, bool adj, int colour, const void* b, v
   if (!x_is_zero) {
     CHK(op_apply<T>(H, l, true, adj, x, b, L.r[prec].p, nrhs));
     r = L.r[prec].p;
+  } else if (H->d.dim != 3) {
+    CHK(launch_zero(x, (int64_t)nrhs * L.vs * csz(prec), H->st));
   }
-  return launch_vanka<T>(largs<T>(H, l, true), H->d.dim, adj, r, x, colour, level_damping(H, l), nrhs, H->st);
+  return launch_vanka<T>(largs<T>(H, l, true), H->d.dim, adj, r, x, colour, level_damping(H, l), nrhs, H->st,
+                         x_is_zero && H->d.dim == 3);
 }
 
 template <typename T>
 static int op_sweeps_from_zero(elh_handle* H, int l, bool adj, const void* b, void* x, int nrhs, int sweeps) {
-  const int prec = sizeof(T) == 8 ? 0 : 1;
-  CHK(launch_zero(x, (int64_t)nrhs * H->lv[l].vs * csz(prec), H->st));
   for (int s = 0; s < sweeps; ++s) {
     CHK(op_relax<T>(H, l, adj, 0, b, x, nrhs, s == 0));
     CHK(op_relax<T>(H, l, adj, 1, b, x, nrhs, false));
@@ -1309,7 +1312,8 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
   if (l == H->nlev - 1) return coarse_solve<T>(H, adj, b, x, nrhs);
   LevelData& L = H->lv[l];
   LevelData& C = H->lv[l + 1];
-  CHK(launch_zero(x, (int64_t)nrhs * L.vs * csz(prec), H->st));
+  // with pre-smoothing the first half-sweep defines every entry of x
+  if (H->d.nu1 == 0) CHK(launch_zero(x, (int64_t)nrhs * L.vs * csz(prec), H->st));
   bool zero = true;
   for (int s = 0; s < H->d.nu1; ++s) {
     CHK(op_relax<T>(H, l, adj, 0, b, x, nrhs, zero));

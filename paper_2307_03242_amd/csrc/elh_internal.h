@@ -17,7 +17,7 @@ int launch_apply(const LevelArgs<T>& L, int dim, bool adj, const void* x, const 
                  hipStream_t st);
 template <typename T>
 int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* x, int colour, double w, int nrhs,
-                 hipStream_t st);
+                 hipStream_t st, bool write = false);  // write: 3D first half-sweep, x not yet set
 template <typename T>
 int launch_restrict(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* r, void* rc, int nrhs,
                     hipStream_t st);

@@ -205,9 +205,14 @@ __global__ void __launch_bounds__(256) k_vanka(LevelArgs<T> L, const cx<T>* __re
 // operator).  The absorbing-layer profile is summed per axis: centre and
 // both face positions once per cell.  Same blocks, Schur complement and
 // update as k_vanka.
-template <bool ADJ, typename T>
+template <bool ADJ, bool WR, typename T>
 __global__ void __launch_bounds__(256) k_vanka3(LevelArgs<T> L, const cx<T>* __restrict__ r, cx<T>* __restrict__ x,
                                                  int colour, T w, int nrhs) {
+  // WR (first half-sweep from a zero iterate): x holds no values yet; the
+  // corrections are written, not added, and every entry that no block of
+  // this colour writes is set to zero here: the cell's own boundary faces,
+  // and the pressure and boundary faces of its two x_1 neighbours (the other
+  // colour; each of those has at least one neighbour of this colour).
   // 32-bit index arithmetic (the launcher checks the cell count fits)
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
@@ -331,17 +336,42 @@ __global__ void __launch_bounds__(256) k_vanka3(LevelArgs<T> L, const cx<T>* __r
   }
   const T is2 = T(1) / abs2(schur);
   const cx<T> dp = rp * mk(schur.re * is2, -schur.im * is2);
-  xs[3 * L.fs + cell] += w * dp;
+  if (!WR) {
+    xs[3 * L.fs + cell] += w * dp;
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd)
-      if (ok[k][sd]) xs[idx[k][sd]] += w * (yr[k][sd] - yg[k][sd] * dp);
+      for (int sd = 0; sd < 2; ++sd)
+        if (ok[k][sd]) xs[idx[k][sd]] += w * (yr[k][sd] - yg[k][sd] * dp);
+    return;
+  }
+  const cx<T> z = czero<T>();
+  xs[3 * L.fs + cell] = w * dp;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (ok[k][0]) xs[idx[k][0]] = w * (yr[k][0] - yg[k][0] * dp);
+    else xs[k * L.fs + cell] = z;  // boundary face
+    if (ok[k][1]) xs[idx[k][1]] = w * (yr[k][1] - yg[k][1] * dp);
+  }
+  if (c[0] >= 1) {
+    const int64_t nb = cell - 1;
+    xs[3 * L.fs + nb] = z;
+    if (c[0] == 1) xs[nb] = z;
+    if (c[1] == 0) xs[L.fs + nb] = z;
+    if (c[2] == 0) xs[2 * L.fs + nb] = z;
+  }
+  if (c[0] + 1 < n0) {
+    const int64_t nb = cell + 1;
+    xs[3 * L.fs + nb] = z;
+    if (c[1] == 0) xs[L.fs + nb] = z;
+    if (c[2] == 0) xs[2 * L.fs + nb] = z;
+  }
 }
 
 template <typename T>
 int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* x, int colour, double w, int nrhs,
-                 hipStream_t st) {
+                 hipStream_t st, bool write) {
+  if (write && dim != 3) return (int)hipErrorInvalidValue;
   const int64_t work = (L.fs / L.n[0]) * ((L.n[0] + 1) / 2);
   // small (coarse) levels: 64-thread workgroups so that every CU gets work
   const int bs = work < 256 * 256 ? 64 : 256;
@@ -350,8 +380,10 @@ int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* 
   cx<T>* xp = (cx<T>*)x;
   if (dim == 3) {
     if (work > 0x7fffffffll || L.fs > 0x7fffffffll) return (int)hipErrorInvalidValue;
-    if (adj) hipLaunchKernelGGL((k_vanka3<true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
-    else hipLaunchKernelGGL((k_vanka3<false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    if (adj && write) hipLaunchKernelGGL((k_vanka3<true, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else if (adj) hipLaunchKernelGGL((k_vanka3<true, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else if (write) hipLaunchKernelGGL((k_vanka3<false, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else hipLaunchKernelGGL((k_vanka3<false, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
   } else {
     if (adj) hipLaunchKernelGGL((k_vanka<2, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
     else hipLaunchKernelGGL((k_vanka<2, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
@@ -359,9 +391,9 @@ int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* 
   return (int)hipGetLastError();
 }
 template int launch_vanka<double>(const LevelArgs<double>&, int, bool, const void*, void*, int, double, int,
-                                  hipStream_t);
+                                  hipStream_t, bool);
 template int launch_vanka<float>(const LevelArgs<float>&, int, bool, const void*, void*, int, double, int,
-                                 hipStream_t);
+                                 hipStream_t, bool);
 
 // ---------------------------------------------------------------------------
 // MAC restriction (one thread per coarse cell) and prolongation (one thread
