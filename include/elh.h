@@ -111,7 +111,7 @@ typedef struct {
   int kacz_box;         /* KACZMARZ: sub-regions are boxes of kacz_box^dim
                            cells (<= 0: 4); the private copy of a sub-region,
                            dim*(kacz_box+4)^dim complex float64, must fit in
-                           64 KiB of LDS (3D: kacz_box <= 6)                  */
+                           64 KiB of LDS (3D: kacz_box <= 7)                  */
 } elh_desc;
 
 typedef struct {

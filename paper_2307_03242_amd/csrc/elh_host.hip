@@ -1167,28 +1167,32 @@ static int gmres_device(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ
   double* gnrm = (double*)H->gnrm.p;
   double* gcoef = (double*)H->gcoef.p;
   double* gscale = (double*)H->gscale.p;
-  CHK(launch_zero(x, vbytes, st));
-  CHK((launch_scale_copy<CT, CT>(nullptr, b, len, w, len, len, nrhs, st)));
+  // x0 = 0: the first residual is b itself, and the first solution update
+  // writes x instead of adding to it
   int done = 0;
+  const CT* r0 = (const CT*)b;
   while (done < maxit) {
-    CHK((launch_multidot<CT, CT>(1, w, 0, len, w, len, len, nrhs, gpart, gnrm, st)));
+    CHK((launch_multidot<CT, CT>(1, r0, 0, len, r0, len, len, nrhs, gpart, gnrm, st)));
     CHK(launch_gm_start(nrhs, gnrm, gst, gscale, st));
-    CHK((launch_scale_copy<CT, CT>(gscale, w, len, V, len, len, nrhs, st)));
+    CHK((launch_scale_copy<CT, CT>(gscale, r0, len, V, len, len, nrhs, st)));
     const int k = (maxit - done) < m ? (maxit - done) : m;
     for (int j = 0; j < k; ++j) {
       CHK(M((const void*)(V + j * vstr), (void*)(Z + j * vstr)));
       CHK(AZ((const void*)(Z + j * vstr), (void*)w));
       CHK((launch_multidot<CT, CT>(j + 1, V, vstr, len, w, len, len, nrhs, gpart, gdots, st)));
       CHK(launch_gm_hcol(nrhs, j, gdots, gst, gcoef, st));
-      CHK((launch_multiaxpy<CT, CT>(j + 1, gcoef, V, vstr, len, w, len, len, nrhs, st)));
-      CHK((launch_multidot<CT, CT>(1, w, 0, len, w, len, len, nrhs, gpart, gnrm, st)));
+      // Gram-Schmidt update and its norm in one pass
+      CHK((launch_axpy_norm<CT, CT>(j + 1, gcoef, V, vstr, len, w, len, nullptr, len, len, nrhs, gpart, gnrm, st)));
       CHK(launch_gm_rotate(nrhs, j, gnrm, gst, gscale, st));
       if (j + 1 < k) CHK((launch_scale_copy<CT, CT>(gscale, w, len, V + (j + 1) * vstr, len, len, nrhs, st)));
     }
     CHK(launch_gm_backsolve(nrhs, k, gst, gcoef, st));
-    CHK((launch_multiaxpy<CT, CT>(k, gcoef, Z, vstr, len, x, len, len, nrhs, st)));
+    CHK((launch_multiaxpy<CT, CT>(k, gcoef, Z, vstr, len, x, len, len, nrhs, st, done == 0)));
     done += k;
-    if (done < maxit) CHK(AR((const void*)x, b, (void*)w));
+    if (done < maxit) {
+      CHK(AR((const void*)x, b, (void*)w));
+      r0 = w;
+    }
   }
   return 0;
 }

@@ -46,7 +46,7 @@ int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_r
                     int64_t wstride_rhs, int64_t len, int nrhs, double* part, double* out, hipStream_t st);
 template <typename TV, typename TW>
 int launch_multiaxpy(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
-                     int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st);
+                     int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st, bool set = false);  // set: w = sum
 // w += sum_i coef_i V_i in place with ||w||^2 per rhs into out[2s] (part:
 // scratch of 512*MAXDOT*2 doubles per rhs); f (optional) receives w in TF.
 template <typename TV, typename TF>

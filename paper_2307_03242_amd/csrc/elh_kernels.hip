@@ -846,16 +846,18 @@ template int launch_multidot<cx<double>, cx<double>>(int, const void*, int64_t, 
 template int launch_multidot<cx<float>, cx<float>>(int, const void*, int64_t, int64_t, const void*, int64_t,
                                                    int64_t, int, double*, double*, hipStream_t);
 
-// w[s] += sum_i coef[s*m+i] * V_i[s]   (coef complex double, on device)
-template <typename TV, typename TW>
+// w[s] += sum_i coef[s*m+i] * V_i[s]   (coef complex double, on device);
+// SET: w[s] = sum_i ... (w is not read)
+template <typename TV, typename TW, bool SET>
 __global__ void __launch_bounds__(256) k_multiaxpy(int m, const double* __restrict__ coef, const TV* __restrict__ V,
                                                     int64_t vstride_vec, int64_t vstride_rhs, TW* __restrict__ w,
                                                     int64_t wstride_rhs, int64_t len) {
   const int s = blockIdx.y;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= len) return;
-  auto wv = w[s * wstride_rhs + t];
-  double re = (double)wv.re, im = (double)wv.im;
+  TW wv;
+  if (!SET) wv = w[s * wstride_rhs + t];
+  double re = SET ? 0.0 : (double)wv.re, im = SET ? 0.0 : (double)wv.im;
   for (int i = 0; i < m; ++i) {
     double cr = coef[(s * m + i) * 2], ci = coef[(s * m + i) * 2 + 1];
     auto vv = V[i * vstride_vec + s * vstride_rhs + t];
@@ -870,17 +872,22 @@ __global__ void __launch_bounds__(256) k_multiaxpy(int m, const double* __restri
 
 template <typename TV, typename TW>
 int launch_multiaxpy(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
-                     int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL((k_multiaxpy<TV, TW>), dim3((unsigned)((len + 255) / 256), nrhs), dim3(256), 0, st, m, coef,
-                     (const TV*)V, vstride_vec, vstride_rhs, (TW*)w, wstride_rhs, len);
+                     int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st, bool set) {
+  const dim3 grd((unsigned)((len + 255) / 256), nrhs), blk(256);
+  if (set)
+    hipLaunchKernelGGL((k_multiaxpy<TV, TW, true>), grd, blk, 0, st, m, coef, (const TV*)V, vstride_vec, vstride_rhs,
+                       (TW*)w, wstride_rhs, len);
+  else
+    hipLaunchKernelGGL((k_multiaxpy<TV, TW, false>), grd, blk, 0, st, m, coef, (const TV*)V, vstride_vec,
+                       vstride_rhs, (TW*)w, wstride_rhs, len);
   return (int)hipGetLastError();
 }
 template int launch_multiaxpy<cx<double>, cx<double>>(int, const double*, const void*, int64_t, int64_t, void*,
-                                                      int64_t, int64_t, int, hipStream_t);
+                                                      int64_t, int64_t, int, hipStream_t, bool);
 template int launch_multiaxpy<cx<float>, cx<double>>(int, const double*, const void*, int64_t, int64_t, void*,
-                                                     int64_t, int64_t, int, hipStream_t);
+                                                     int64_t, int64_t, int, hipStream_t, bool);
 template int launch_multiaxpy<cx<float>, cx<float>>(int, const double*, const void*, int64_t, int64_t, void*,
-                                                    int64_t, int64_t, int, hipStream_t);
+                                                    int64_t, int64_t, int, hipStream_t, bool);
 
 // Gram-Schmidt update fused with its norm: w[s] += sum_i coef[s*m+i] V_i[s]
 // in place, part[] receives per-block partial sums of |w|^2 (entries 2b and

@@ -136,3 +136,33 @@ def test_mixed_precision_solve_with_kaczmarz_coarse_solve():
     assert code == 0 and info[0]["status"] == 0 and info[0]["relres"] <= 1e-6
     r = prob.residual(q.cuda(), u)
     assert (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(q)).item() <= 1e-6 * (1 + 1e-6)
+
+
+def test_kaczmarz_argument_errors():
+    """the Kaczmarz entry point and descriptor checks reject bad input
+    before anything is launched"""
+    from paper_2307_03242_amd import Problem
+    from paper_2307_03242_amd._lib import ElhError
+    shape = (8, 8, 8)
+    prob, lv = _setup(shape, 2)
+    b = _dev(random_field(shape, 1))
+    x = torch.empty_like(b)
+    lib, h = prob.lib, prob.handle
+    assert lib.elh_kaczmarz(h, 0, 2, 1, 0, b.data_ptr(), x.data_ptr()) == -1      # no sweep
+    assert lib.elh_kaczmarz(h, 0, 2, 1, 3, b.data_ptr(), b.data_ptr()) == -1      # aliasing
+    assert lib.elh_kaczmarz(h, 0, 2, 65, 3, b.data_ptr(), x.data_ptr()) == -1     # too many rhs
+    m = make_media(shape, 6)
+    med = [torch.from_numpy(m[k]) for k in ("lam", "mu", "rho")]
+    other = Problem(*med, levels=1, coarse_mode="krylov")
+    assert other.lib.elh_kaczmarz(other.handle, 0, 2, 1, 3, b.data_ptr(), x.data_ptr()) == -1  # wrong mode
+    with pytest.raises(ElhError):
+        Problem(*med, levels=1, coarse_mode="kaczmarz", kacz_box=8)  # private copy 3*12^3*16 B exceeds 64 KiB
+    with pytest.raises(ElhError):
+        Problem(*med, levels=1, coarse_mode="kaczmarz", kacz_box=-1)
+    # the float32-input outer operator: complex64 in, complex128 out, unshifted
+    x32 = b.to(torch.complex64)
+    with pytest.raises(TypeError):
+        prob.apply_f32_input(b)
+    y = torch.empty_like(b)
+    assert lib.elh_apply_f32in(h, 1, 1, x32.data_ptr(), y.data_ptr()) == -1  # ELH_SHIFTED
+    assert lib.elh_apply_f32in(h, 0, 1, x32.data_ptr(), x32.data_ptr()) == -1
