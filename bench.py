@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--pmc-target", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration) and the float32 residual at "
                          "--n^3, three launches each, for rocprofv3 --pmc passes")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="only the 2D iteration-count experiments of the paper's homogeneous and linear-media "
+                         "tables (W(1,1) cycles, 2-4 levels, beta 1 and 2/3), counts beside the printed ones")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-sources, uneven-batch and gradient measurements")
     return ap.parse_args()
@@ -261,6 +264,78 @@ def extras(args):
     return out
 
 
+# The paper's 2D iteration counts (Section 5.2): FGMRES(5) preconditioner
+# cycles to 1e-6 with W(1,1) on the shifted operator, per grid and column
+# (beta, G_s, levels, alpha); counts for the homogeneous model (lambda = 20,
+# mu = rho = 1) and for the linear model (rho 2..3, lambda 4..20, mu 1..15).
+PAPER_COLUMNS = [(1.0, 10, 2, 0.1), (1.0, 10, 3, 0.4), (1.0, 10, 4, 0.5),
+                 (2 / 3, 10, 2, 0.1), (2 / 3, 10, 3, 0.3), (2 / 3, 10, 4, 0.4),
+                 (2 / 3, 8, 2, 0.1), (2 / 3, 8, 3, 0.5), (2 / 3, 8, 4, 0.5)]
+PAPER_COLUMNS_LINEAR = [(1.0, 10, 2, 0.1), (1.0, 10, 3, 0.4), (1.0, 10, 4, 0.5),
+                        (2 / 3, 10, 2, 0.1), (2 / 3, 10, 3, 0.3), (2 / 3, 10, 4, 0.4),
+                        (2 / 3, 8, 2, 0.1), (2 / 3, 8, 3, 0.4), (2 / 3, 8, 4, 0.5)]
+PAPER_COUNTS = {
+    "homogeneous": {(128, 512): [39, 131, 160, 22, 86, 143, 27, 144, 171],
+                    (256, 1024): [56, 199, 243, 32, 135, 222, 39, 231, 269],
+                    (512, 2048): [79, 256, 332, 40, 144, 275, 50, 294, 294]},
+    "linear": {(128, 512): [39, 134, 169, 24, 77, 133, 31, 134, 181],
+               (256, 1024): [59, 265, 333, 34, 134, 260, 40, 219, 337],
+               (512, 2048): [80, 396, 452, 42, 153, 379, 52, 266, 479]},
+}
+
+
+def paper_tables(args):
+    """Readings: h = 1 (grid units); absorbing layer of 20 cells on every
+    side; one u_2 point source in the middle of the top row; the coarsest
+    solve (LU in the paper) replaced by Vanka-preconditioned GMRES to a 1e-8
+    residual drop; float64 cycle.  Only the 3- and 4-level columns on the
+    two smaller grids: with 2 levels the coarsest grid is a 5-points-per-
+    wavelength Helmholtz problem at shift 0.1, which the iterative stand-in
+    for LU does not solve."""
+    import numpy as np
+    import torch
+    from paper_2307_03242_amd import Problem
+    from synthetic import constant_media, linear_media, omega_for_ppw
+    out = {}
+    for model in ("homogeneous", "linear"):
+        cols = PAPER_COLUMNS if model == "homogeneous" else PAPER_COLUMNS_LINEAR
+        rows = {}
+        for shape, printed in PAPER_COUNTS[model].items():
+            if shape[1] > 1024:
+                continue
+            if model == "homogeneous":
+                m = constant_media(shape, 20.0, 1.0, 1.0)
+            else:
+                m = linear_media(shape, (4.0, 20.0), (1.0, 15.0), (2.0, 3.0))
+            vs_min = float(np.sqrt(m["mu"] / m["rho"]).min())
+            med = [torch.from_numpy(m[k]) for k in ("lam", "mu", "rho")]
+            q = torch.zeros((1, 3) + shape, dtype=torch.complex128)
+            q[0, 1, 1, shape[1] // 2] = 1.0
+            q = q.cuda()
+            got = []
+            for (beta, gs, levels, alpha) in cols:
+                if levels == 2:
+                    got.append(None)
+                    continue
+                prob = Problem(*med, h=1.0, omega=omega_for_ppw(vs_min, 1.0, gs), gamma=0.01, alpha=alpha,
+                               beta=beta, abl_width=20.0, abl_amp=2.0, levels=levels, nu1=1, nu2=1, cycle="W",
+                               damping=(0.55, 0.35, 0.25), coarse_mode="krylov", coarse_sweeps=2,
+                               coarse_restart=10, coarse_maxit=400, coarse_rtol=1e-8,
+                               precond_dtype=torch.complex128)
+                _, info, code = prob.solve(q, rtol=1e-6, maxit=600)
+                got.append(info[0]["iters"] if code == 0 else None)
+                prob.close()
+                print("%s %dx%d beta=%.3f Gs=%d levels=%d alpha=%.2f: %s (paper %d)"
+                      % (model, shape[1], shape[0], beta, gs, levels, alpha, got[-1], printed[len(got) - 1]),
+                      file=sys.stderr, flush=True)
+            rows["%dx%d" % (shape[1], shape[0])] = {"ours": got, "paper": printed,
+                                                    "ratio": [None if g is None else round(g / p, 3)
+                                                              for g, p in zip(got, printed)]}
+        out[model] = {"columns": [{"beta": round(b, 4), "G_s": g, "levels": l, "alpha": a} for b, g, l, a in cols],
+                      "rows": rows}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -273,6 +348,9 @@ def main():
     from synthetic import make_media, point_source, omega_for_ppw
 
     torch.cuda.set_device(0)
+    if args.paper_tables:
+        print(json.dumps({"paper_tables": paper_tables(args)}), flush=True)
+        return
     n = args.n
     shape = (n, n, n)
     m = make_media(shape, args.seed)
