@@ -13,9 +13,12 @@ E(theta) is the symbol matrix of eq. symbolTG, of size 2^d (d+1):
     2h along its face axis and at an odd multiple of h along the others,
     which gives harmonic a the sign s(a, f) = prod over those axes of
     (-1)^{a_b};
-  * S: the smoother.  The paper analyses lexicographic (economic) Vanka,
-    whose symbol it does not print; the build's production smoother is
-    red-black full Vanka, whose symbol is derived here.  One colour's
+  * S: the smoother.  Two are analysed here.  The paper's LFA (Sections
+    4.3 and 5.1) uses economic Vanka (the displacement part of each cell
+    block replaced by its diagonal, Section 2.3) swept over the cells in
+    lexicographic order; it omits the symbol's derivation, which is given
+    in `LexVanka` below.  The build's production smoother is red-black
+    full Vanka, whose symbol is derived next.  One colour's
     half-sweep e <- e - w B_c A e solves every cell block of colour c with
     the residual; on a plane wave it returns the same wave plus the wave
     shifted by (pi,...,pi), because the colour indicator is
@@ -217,7 +220,19 @@ def _sign(a, f, d):
 
 
 class LFA:
-    def __init__(self, dim, h, omega, gamma, beta, lam, mu, rho, alpha, w, nu1=1, nu2=1, cell_block=None):
+    def __init__(self, dim, h, omega, gamma, beta, lam, mu, rho, alpha, w, nu1=1, nu2=1, cell_block=None,
+                 smoother="red-black", scalar_smoother=False):
+        """smoother: "red-black" (full Vanka, the production smoother),
+        "lex-economic" or "lex-full" (lexicographic sweeps, `LexVanka`).
+
+        scalar_smoother (lexicographic smoothers only): the paper's reading
+        of its smoothing symbol matrix (eq. smoothingSymbolMatrix), which
+        puts one scalar per harmonic on the diagonal.  The scalar taken is
+        the eigenvalue of largest modulus of the (d+1)x(d+1) sweep symbol at
+        that harmonic, acting on all d+1 fields alike.  This is not the
+        two-grid operator of the cycle (that is scalar_smoother=False, which
+        the periodic assembly pins); it is the reading under which the
+        two-grid factors printed in Table 1 are reproduced."""
         self.d = dim
         self.h, self.omega, self.gamma, self.beta = h, omega, gamma, beta
         self.lam, self.mu, self.rho = lam, mu, rho
@@ -227,6 +242,13 @@ class LFA:
             cell_block = vanka_cell_block(prob, alpha)
         self.Acell_inv = np.linalg.inv(cell_block)
         self.H = _harmonics(dim)
+        assert smoother in ("red-black", "lex-economic", "lex-full")
+        self.kind = smoother
+        assert not (scalar_smoother and smoother == "red-black")
+        self.scalar_smoother = scalar_smoother
+        if smoother != "red-black":
+            self.lex = LexVanka(PeriodicProblem(8, dim, h, omega, gamma, beta, lam, mu, rho), alpha, w,
+                                economic=smoother == "lex-economic")
 
     def A_sym(self, th, shifted=True, coarse=False):
         g = self.gamma + (self.alpha if shifted else 0.0)
@@ -293,7 +315,18 @@ class LFA:
         return np.eye(size) - self.w * M
 
     def smoother(self, theta):
-        return self.half_sweep(theta, 1) @ self.half_sweep(theta, 0)
+        if self.kind == "red-black":
+            return self.half_sweep(theta, 1) @ self.half_sweep(theta, 0)
+        # a lexicographic sweep maps each harmonic to itself
+        nf = self.d + 1
+        M = np.zeros((len(self.H) * nf,) * 2, dtype=complex)
+        for ai, a in enumerate(self.H):
+            Sa = self.lex.symbol(theta + np.pi * a)
+            if self.scalar_smoother:
+                ev = np.linalg.eigvals(Sa)
+                Sa = ev[np.argmax(np.abs(ev))] * np.eye(nf)
+            M[ai * nf:(ai + 1) * nf, ai * nf:(ai + 1) * nf] = Sa
+        return M
 
     def two_grid(self, theta):
         theta = np.asarray(theta, dtype=float)
@@ -303,9 +336,53 @@ class LFA:
         Sm = self.smoother(theta)
         return np.linalg.matrix_power(Sm, self.nu2) @ K @ np.linalg.matrix_power(Sm, self.nu1)
 
+    def _lex_blocks(self, th):
+        """(m, d+1, d+1) smoother blocks of a lexicographic sweep at the rows
+        of th, under the chosen reading"""
+        Sa = self.lex.symbol(th)
+        if self.scalar_smoother:
+            ev = np.linalg.eigvals(Sa)
+            pick = ev[np.arange(len(ev)), np.argmax(np.abs(ev), axis=1)]
+            Sa = pick[:, None, None] * np.eye(self.d + 1)
+        return Sa
+
+    def two_grid_many(self, thetas):
+        """TG at every row of an (m, d) array (lexicographic smoothers): the
+        same matrices as `two_grid`, built for all m frequencies at once"""
+        th = np.atleast_2d(np.asarray(thetas, dtype=float))
+        m, d, nf = th.shape[0], self.d, self.d + 1
+        n = len(self.H) * nf
+        Ah = np.zeros((m, n, n), dtype=complex)
+        Sm = np.zeros((m, n, n), dtype=complex)
+        R = np.zeros((m, nf, n))
+        P = np.zeros((m, n, nf))
+        for ai, a in enumerate(self.H):
+            ta = th + np.pi * a
+            sl = slice(ai * nf, (ai + 1) * nf)
+            Ah[:, sl, sl] = np.moveaxis(self.A_sym(ta.T), -1, 0)
+            rs = S.restriction_symbol(ta.T)
+            ps = S.prolongation_symbol(ta.T)
+            for f in range(nf):
+                R[:, f, self._idx(ai, f)] = rs[f] * _sign(a, f, d)
+                P[:, self._idx(ai, f), f] = ps[f] * _sign(a, f, d) / 2 ** d
+            Sm[:, sl, sl] = self._lex_blocks(ta)
+        Ac = np.moveaxis(self.A_sym((2 * th).T, coarse=True), -1, 0)
+        K = np.eye(n) - P @ np.linalg.solve(Ac, R @ Ah)
+        return np.linalg.matrix_power(Sm, self.nu2) @ K @ np.linalg.matrix_power(Sm, self.nu1)
+
     def rho_loc(self, step=None, thetas=None):
         """max spectral radius of TG(theta) over theta in T_low (a grid with
         spacing `step`, or the given list)."""
+        if self.kind != "red-black":
+            if thetas is None:
+                g = np.arange(-np.pi / 2, np.pi / 2, step)
+                thetas = np.array(list(itertools.product(g, repeat=self.d)))
+            th = np.asarray(list(thetas), dtype=float)
+            best = 0.0
+            for c in range(0, len(th), 8192):
+                ev = np.linalg.eigvals(self.two_grid_many(th[c:c + 8192]))
+                best = max(best, float(np.abs(ev).max()))
+            return best
         if thetas is None:
             g = np.arange(-np.pi / 2, np.pi / 2, step)
             thetas = itertools.product(g, repeat=self.d)
@@ -324,6 +401,15 @@ class LFA:
         of the smoother restricted to the high harmonics (ideal coarse-grid
         correction removes the low harmonic of every E(theta))."""
         g = np.arange(-np.pi / 2, np.pi / 2, step)
+        if self.kind != "red-black":
+            # the sweep keeps each harmonic: its high-frequency symbols directly
+            th = np.array(list(itertools.product(g, repeat=self.d)))
+            best = 0.0
+            for a in self.H[1:]:
+                for c in range(0, len(th), 65536):
+                    ev = np.linalg.eigvals(self.lex.symbol(th[c:c + 65536] + np.pi * a))
+                    best = max(best, float(np.abs(ev).max()))
+            return best
         nf = self.d + 1
         Q = np.eye(len(self.H) * nf)
         Q[:nf, :nf] = 0.0                      # projector onto the high harmonics
@@ -333,3 +419,150 @@ class LFA:
             ev = np.linalg.eigvals(Q @ Sm)
             best = max(best, float(np.abs(ev).max()))
         return best
+
+
+# ----------------------------------------------------------------------------
+# lexicographic cell-wise Vanka (full or economic)
+# ----------------------------------------------------------------------------
+def economic_block(block, dim):
+    """economic Vanka's block (Section 2.3): the cell block with every
+    displacement-displacement entry off the diagonal dropped; the pressure
+    row and column are kept."""
+    B = np.array(block, dtype=complex, copy=True)
+    nu = 2 * dim
+    for a in range(nu):
+        for b in range(nu):
+            if a != b:
+                B[a, b] = 0.0
+    return B
+
+
+def lex_sweep(prob, shift, w, e, economic=True):
+    """one lexicographic Vanka sweep on the error equation of the periodic
+    grid, written out: cells in C order (x_1 fastest); each cell's 2d+1
+    unknowns are corrected by w B^{-1} r with the residual r = -A e taken
+    at that moment, so faces shared with an earlier cell see its update."""
+    A = prob.operator(shift).tocsr()
+    dofs, _ = prob.cell_dofs()
+    e = np.array(e, dtype=complex, copy=True)
+    for dv in dofs:
+        blk = A[dv][:, dv].toarray()
+        B = economic_block(blk, prob.dim) if economic else blk
+        r = -(A[dv] @ e)
+        e[dv] += w * np.linalg.solve(B, r)
+    return e
+
+
+class LexVanka:
+    """Symbol of one lexicographic sweep of cell-wise Vanka.
+
+    Cell c's block holds, for each axis k, the face on its low side L_k
+    (shared with the earlier cell c - e_k) and on its high side R_k (shared
+    with the later cell c + e_k), and its pressure.  A sweep therefore
+    leaves every face in one of three states: old (no cell touched it yet),
+    mid (its low-side cell corrected it) and new (both cells did); a
+    pressure is old or new.  On an infinite grid with a plane-wave error
+    exp(i theta.x/h) every state of every field is the same plane wave with
+    its own amplitude.  When cell c is relaxed:
+      * the residual on its block rows reads each stencil neighbour in the
+        state the lexicographic order gives it at that moment;
+      * L_k goes mid -> new, R_k old -> mid, p old -> new, by w B^{-1} r.
+    These 2d+1 equations are linear in the unknown amplitudes
+    z = (new_1..new_d, mid_1..mid_d, new_p) given the old ones o, and
+    S(theta) is the map o -> (new_1..new_d, new_p).  The stencil and the
+    block come from the periodic assembly, so the symbol uses the operator
+    the cycle uses; `lex_sweep` is the direct counterpart it is checked
+    against."""
+
+    def __init__(self, prob, shift, w, economic=True):
+        d, n = prob.dim, prob.n
+        assert n >= 6
+        self.d, self.w = d, w
+        A = prob.operator(shift).tocsr()
+        N = n ** d
+        centre = np.full(d, n // 2)
+        lin = lambda v: sum(int(v[a]) * n ** a for a in range(d))
+        rows = []
+        for g in range(d + 1):
+            j = g * N + lin(centre)
+            ent = []
+            for ptr in range(A.indptr[j], A.indptr[j + 1]):
+                f, q = divmod(int(A.indices[ptr]), N)
+                idx = np.array([(q // n ** a) % n for a in range(d)])
+                ent.append((f, idx - centre, A.data[ptr]))
+            rows.append(ent)
+        dofs, _ = prob.cell_dofs()
+        blk = A[dofs[lin(centre)]][:, dofs[lin(centre)]].toarray()
+        self.Binv = np.linalg.inv(economic_block(blk, d) if economic else blk)
+        eye = np.eye(d, dtype=np.int64)
+        slots = []
+        for k in range(d):
+            slots += [(k, np.zeros(d, dtype=np.int64)), (k, eye[k])]
+        slots.append((d, np.zeros(d, dtype=np.int64)))
+        self.slots = slots
+        # each residual term: (slot, unknown vector 'z' or 'o', its index,
+        # coefficient, the neighbour's position in units of h)
+        self.terms = []
+        for s, (g, j) in enumerate(slots):
+            for f, off, a in rows[g]:
+                i = j + off
+                where, idx = self._amp(f, i)
+                self.terms.append((s, where, idx, a, self._pos(f, i)))
+
+    def _pos(self, f, i):
+        x = i.astype(float)
+        if f < self.d:
+            x[f] -= 0.5
+        return x
+
+    @staticmethod
+    def _before(v):
+        """is the cell at offset v relaxed before the cell at the origin
+        (lexicographic order, x_1 fastest)?"""
+        for a in reversed(range(len(v))):
+            if v[a] != 0:
+                return v[a] < 0
+        return False
+
+    def _amp(self, f, i):
+        d = self.d
+        if f == d:
+            return ("z", 2 * d) if self._before(i) else ("o", d)
+        if self._before(i):
+            return ("z", f)
+        lo = i.copy()
+        lo[f] -= 1
+        if self._before(lo):
+            return ("z", d + f)
+        return ("o", f)
+
+    def symbol(self, theta):
+        """the (d+1)x(d+1) symbol at theta (a d-vector), or an (m, d+1, d+1)
+        stack at the rows of an (m, d) array"""
+        th = np.asarray(theta, dtype=float)
+        one = th.ndim == 1
+        th = np.atleast_2d(th)
+        m, d = th.shape[0], self.d
+        nz = 2 * d + 1
+        Rz = np.zeros((m, nz, nz), dtype=complex)
+        Ro = np.zeros((m, nz, d + 1), dtype=complex)
+        for s, where, idx, a, x in self.terms:
+            ph = np.exp(1j * (th @ x))
+            if where == "z":
+                Rz[:, s, idx] -= a * ph
+            else:
+                Ro[:, s, idx] -= a * ph
+        E = np.zeros((m, nz, nz), dtype=complex)
+        F = np.zeros((m, nz, d + 1), dtype=complex)
+        for k in range(d):
+            pl = np.exp(-0.5j * th[:, k])   # L_k sits at -e_k/2
+            pr = np.exp(0.5j * th[:, k])    # R_k at +e_k/2
+            E[:, 2 * k, k] = pl
+            E[:, 2 * k, d + k] = -pl
+            E[:, 2 * k + 1, d + k] = pr
+            F[:, 2 * k + 1, k] = pr
+        E[:, 2 * d, 2 * d] = 1.0
+        F[:, 2 * d, d] = 1.0
+        z = np.linalg.solve(E - self.w * self.Binv @ Rz, F + self.w * self.Binv @ Ro)
+        out = z[:, list(range(d)) + [2 * d], :]
+        return out[0] if one else out

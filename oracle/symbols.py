@@ -23,6 +23,8 @@ of weight*exp(i theta.offset/h); prolongation uses the transposed stencil):
   P_p     = prod_m (3 cos(theta_m/2) + cos(3 theta_m/2))/2
 (eq. Ru1Symbol prints R_{u_1} without its 1/8 factor and with a dropped
 '+'; its value times 1/8 equals the formula above.)
+theta is a d-vector, or a (d, m) array of m frequencies; the results then
+carry a trailing axis of length m.
 """
 import numpy as np
 
@@ -48,7 +50,7 @@ def operator_symbol(theta, h, omega, gamma, beta, lam, mu, rho):
     g = [2j / h * np.sin(th[k] / 2.0) for k in range(d)]
     lap = sum(4.0 / h ** 2 * np.sin(th[k] / 2.0) ** 2 * s[k] for k in range(d))
     mass = omega ** 2 * (1 - 1j * gamma) * (beta + (1 - beta) / d * sum(np.cos(th[k]) for k in range(d)))
-    H = np.zeros((d + 1, d + 1), dtype=np.complex128)
+    H = np.zeros((d + 1, d + 1) + th.shape[1:], dtype=np.complex128)
     for k in range(d):
         H[k, k] = mu * lap - rho * mass
         H[k, d] = g[k]
@@ -60,7 +62,7 @@ def operator_symbol(theta, h, omega, gamma, beta, lam, mu, rho):
 def restriction_symbol(theta):
     th = np.asarray(theta, dtype=np.float64)
     d = th.shape[0]
-    out = np.zeros(d + 1)
+    out = np.zeros((d + 1,) + th.shape[1:])
     for f in range(d + 1):
         v = 1.0
         for m in range(d):
@@ -72,7 +74,7 @@ def restriction_symbol(theta):
 def prolongation_symbol(theta):
     th = np.asarray(theta, dtype=np.float64)
     d = th.shape[0]
-    out = np.zeros(d + 1)
+    out = np.zeros((d + 1,) + th.shape[1:])
     for f in range(d + 1):
         v = 1.0
         for m in range(d):
