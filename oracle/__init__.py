@@ -24,7 +24,11 @@ Contents (each module cites the passage it follows):
              sub-region parallel) Kaczmarz sweeps
   adjoint    adjoint solve, misfit and parameter gradient
   symbols    closed-form Fourier symbols of the constant-coefficient blocks
-  lfa        two-grid local Fourier analysis (Section 4)
+  lfa        two-grid local Fourier analysis (Section 4): red-black full
+             Vanka (the production smoother) and the paper's lexicographic
+             economic Vanka
+  lfa_tables the paper's LFA numbers (Table 1, Figures 3-4) and a 3D
+             tuning table, printed by `python -m oracle.lfa_tables`
 
 Parity status of every function is listed in the module headers; a function
 without an independent pin says "parity unpinned".

@@ -1172,18 +1172,24 @@ static int gmres_device(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ
   int done = 0;
   const CT* r0 = (const CT*)b;
   while (done < maxit) {
-    CHK((launch_multidot<CT, CT>(1, r0, 0, len, r0, len, len, nrhs, gpart, gnrm, st)));
-    CHK(launch_gm_start(nrhs, gnrm, gst, gscale, st));
+    // small reductions are finished by their consumer (no separate launch)
+    const bool fn = nrhs * 2 <= FUSE_VALS;
+    const int nbn = norm_blocks(len, FUSE_BLOCKS);
+    CHK((launch_multidot<CT, CT>(1, r0, 0, len, r0, len, len, nrhs, gpart, fn ? nullptr : gnrm, st)));
+    CHK(launch_gm_start(nrhs, fn ? nullptr : gnrm, fn ? gpart : nullptr, multidot_blocks(1, len, FUSE_BLOCKS), gst, gscale, st));
     CHK((launch_scale_copy<CT, CT>(gscale, r0, len, V, len, len, nrhs, st)));
     const int k = (maxit - done) < m ? (maxit - done) : m;
     for (int j = 0; j < k; ++j) {
       CHK(M((const void*)(V + j * vstr), (void*)(Z + j * vstr)));
       CHK(AZ((const void*)(Z + j * vstr), (void*)w));
-      CHK((launch_multidot<CT, CT>(j + 1, V, vstr, len, w, len, len, nrhs, gpart, gdots, st)));
-      CHK(launch_gm_hcol(nrhs, j, gdots, gst, gcoef, st));
+      const bool fd = nrhs * 2 * (j + 1) <= FUSE_VALS;
+      CHK((launch_multidot<CT, CT>(j + 1, V, vstr, len, w, len, len, nrhs, gpart, fd ? nullptr : gdots, st)));
+      CHK(launch_gm_hcol(nrhs, j, fd ? nullptr : gdots, fd ? gpart : nullptr, multidot_blocks(j + 1, len, FUSE_BLOCKS), gst, gcoef,
+                         st));
       // Gram-Schmidt update and its norm in one pass
-      CHK((launch_axpy_norm<CT, CT>(j + 1, gcoef, V, vstr, len, w, len, nullptr, len, len, nrhs, gpart, gnrm, st)));
-      CHK(launch_gm_rotate(nrhs, j, gnrm, gst, gscale, st));
+      CHK((launch_axpy_norm<CT, CT>(j + 1, gcoef, V, vstr, len, w, len, nullptr, len, len, nrhs, gpart,
+                                    fn ? nullptr : gnrm, st)));
+      CHK(launch_gm_rotate(nrhs, j, fn ? nullptr : gnrm, fn ? gpart : nullptr, nbn, gst, gscale, st));
       if (j + 1 < k) CHK((launch_scale_copy<CT, CT>(gscale, w, len, V + (j + 1) * vstr, len, len, nrhs, st)));
     }
     CHK(launch_gm_backsolve(nrhs, k, gst, gcoef, st));
@@ -1348,13 +1354,18 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
     CHK(launch_restrict<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, r, R1, nrhs, H->st));
     CHK(cycle<T>(H, l + 1, adj, R1, E1, nrhs));
     CHK(op_apply<T>(H, l + 1, true, adj, E1, nullptr, V1, nrhs));
-    CHK((launch_multidot<CT, CT>(2, V1, vec, C.vs, V1, C.vs, C.vs, nrhs, (double*)H->part.p, kd, H->st)));
-    CHK(launch_kcycle_coef(1, kd, kc1, ks, nrhs, H->st));
+    // the coefficient kernels finish small reductions themselves
+    double* kp = (double*)H->part.p;
+    const bool f1 = nrhs * 4 <= FUSE_VALS, f2 = nrhs * 6 <= FUSE_VALS;
+    CHK((launch_multidot<CT, CT>(2, V1, vec, C.vs, V1, C.vs, C.vs, nrhs, kp, f1 ? nullptr : kd, H->st)));
+    CHK(launch_kcycle_coef(1, f1 ? nullptr : kd, f1 ? kp : nullptr, multidot_blocks(2, C.vs, FUSE_BLOCKS), kc1, ks, nrhs,
+                              H->st));
     CHK((launch_multiaxpy<CT, CT>(1, kc1, V1, 0, C.vs, R1, C.vs, C.vs, nrhs, H->st)));
     CHK(cycle<T>(H, l + 1, adj, R1, E2, nrhs));
     CHK(op_apply<T>(H, l + 1, true, adj, E2, nullptr, V2, nrhs));
-    CHK((launch_multidot<CT, CT>(3, V1, vec, C.vs, V2, C.vs, C.vs, nrhs, (double*)H->part.p, kd, H->st)));
-    CHK(launch_kcycle_coef(2, kd, kc2, ks, nrhs, H->st));
+    CHK((launch_multidot<CT, CT>(3, V1, vec, C.vs, V2, C.vs, C.vs, nrhs, kp, f2 ? nullptr : kd, H->st)));
+    CHK(launch_kcycle_coef(2, f2 ? nullptr : kd, f2 ? kp : nullptr, multidot_blocks(3, C.vs, FUSE_BLOCKS), kc2, ks, nrhs,
+                              H->st));
     CHK(launch_zero(C.x[prec].p, (int64_t)nrhs * C.vs * csz(prec), H->st));
     CHK((launch_multiaxpy<CT, CT>(2, kc2, E1, 4 * vec, C.vs, C.x[prec].p, C.vs, C.vs, nrhs, H->st)));
   } else {

@@ -53,8 +53,19 @@ template <typename TV, typename TF>
 int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_vec, int64_t vstride_rhs, void* w,
                      int64_t wstride_rhs, void* f, int64_t fstride_rhs, int64_t len, int nrhs, double* part,
                      double* out, hipStream_t st);
+// Reductions: launch_multidot / launch_axpy_norm leave per-block partials in
+// `part` and, unless `out` is null, reduce them into `out`.  With `out` null
+// they use at most FUSE_BLOCKS blocks per rhs (multidot_blocks(m, len,
+// FUSE_BLOCKS) / norm_blocks(len, FUSE_BLOCKS)), and the consumer below,
+// given the partials instead of `out`, finishes the reduction; this is for
+// reductions of at most FUSE_VALS values (nrhs * 2m).
+constexpr int FUSE_VALS = 16;
+constexpr int FUSE_BLOCKS = 1024;
+int multidot_blocks(int m, int64_t len, int cap);
+int norm_blocks(int64_t len, int cap);
 // K-cycle step coefficients from the dots (stage 1: m = 2, stage 2: m = 3).
-int launch_kcycle_coef(int stage, const double* dots, double* coef, double* state, int nrhs, hipStream_t st);
+int launch_kcycle_coef(int stage, const double* dots, const double* part, int nb, double* coef, double* state,
+                       int nrhs, hipStream_t st);
 template <typename TX, typename TY>
 int launch_scale_copy(const double* a, const void* x, int64_t xstride, void* y, int64_t ystride, int64_t len,
                       int nrhs, hipStream_t st);
@@ -97,9 +108,12 @@ int launch_kacz_spmv(const KaczArgs<T>& K, const void* x, const void* b, void* y
 template <typename T>
 int launch_kacz_elem(int mode, int dim, int64_t fs, int64_t vs, int nrhs, const void* app, int cj, const void* b,
                      const void* y, void* out, hipStream_t st);
-int launch_gm_start(int nrhs, const double* nrm2, double* st, double* scale, hipStream_t s);
-int launch_gm_hcol(int nrhs, int j, const double* dots, double* st, double* coef, hipStream_t s);
-int launch_gm_rotate(int nrhs, int j, const double* nrm2, double* st, double* scale, hipStream_t s);
+int launch_gm_start(int nrhs, const double* nrm2, const double* part, int nb, double* st, double* scale,
+                    hipStream_t s);
+int launch_gm_hcol(int nrhs, int j, const double* dots, const double* part, int nb, double* st, double* coef,
+                   hipStream_t s);
+int launch_gm_rotate(int nrhs, int j, const double* nrm2, const double* part, int nb, double* st, double* scale,
+                     hipStream_t s);
 int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStream_t s);
 
 }  // namespace elh

@@ -819,13 +819,55 @@ __global__ void __launch_bounds__(256) k_reduce_parts(int m2, int nblocks, const
   if (threadIdx.x == 0) out[(int64_t)s * m2 + e] = red[0];
 }
 
+int multidot_blocks(int m, int64_t len, int cap) {
+  int64_t nb = (len + RED_THREADS - 1) / RED_THREADS;
+  if (nb > RED_PAIRS / m) nb = RED_PAIRS / m;
+  if (nb > cap) nb = cap;
+  return nb < 1 ? 1 : (int)nb;
+}
+int norm_blocks(int64_t len, int cap) {
+  int64_t nb = (len + RED_THREADS - 1) / RED_THREADS;
+  if (nb > RED_PAIRS) nb = RED_PAIRS;
+  if (nb > cap) nb = cap;
+  return nb < 1 ? 1 : (int)nb;
+}
+
+// The consumers of a small reduction (GMRES bookkeeping, K-cycle
+// coefficients: at most FUSE_VALS values, whose producers were launched with
+// at most FUSE_BLOCKS blocks) finish it themselves, which saves one launch
+// per reduction.  The block of 256 threads splits into one group per value
+// (a power of two of threads each); a group sums its value's partials
+// strided, then a fixed tree inside the group.  Otherwise `out` holds the
+// values reduced by k_reduce_parts.  Every thread of the block must call
+// this before any early return.
+__device__ const double* small_reduction(int nv, int m2, const double* __restrict__ out,
+                                         const double* __restrict__ part, int nb, double* vals) {
+  if (!part) return out;
+  __shared__ double red[256];
+  int gs = 256;  // threads per value
+  while (gs > 16 && 256 / gs < nv) gs >>= 1;
+  const int v = threadIdx.x / gs, lane = threadIdx.x - v * gs;
+  double acc = 0.0;
+  if (v < nv) {
+    const int sv = v / m2, e = v - sv * m2;
+    for (int b = lane; b < nb; b += gs) acc += part[((int64_t)sv * nb + b) * m2 + e];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = gs / 2; o > 0; o >>= 1) {
+    if (lane < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (v < nv && lane == 0) vals[v] = red[threadIdx.x];
+  __syncthreads();
+  return vals;
+}
+
 template <typename TV, typename TW>
 int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_rhs, const void* w,
                     int64_t wstride_rhs, int64_t len, int nrhs, double* part, double* out, hipStream_t st) {
   if (m < 1 || m > MAXDOT) return (int)hipErrorInvalidValue;
-  int nb = (int)((len + RED_THREADS - 1) / RED_THREADS);
-  if (nb > RED_PAIRS / m) nb = RED_PAIRS / m;
-  if (nb < 1) nb = 1;
+  const int nb = multidot_blocks(m, len, out ? RED_PAIRS : FUSE_BLOCKS);
   const dim3 grd(nb, nrhs), blk(RED_THREADS);
   const TV* Vp = (const TV*)V;
   const TW* wp = (const TW*)w;
@@ -838,7 +880,7 @@ int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_r
     case 6: hipLaunchKernelGGL((k_multidot<TV, TW, 6>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
     default: hipLaunchKernelGGL((k_multidot<TV, TW, 0>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part);
   }
-  hipLaunchKernelGGL(k_reduce_parts, dim3(2 * m, nrhs), dim3(256), 0, st, 2 * m, nb, part, out);
+  if (out) hipLaunchKernelGGL(k_reduce_parts, dim3(2 * m, nrhs), dim3(256), 0, st, 2 * m, nb, part, out);
   return (int)hipGetLastError();
 }
 template int launch_multidot<cx<double>, cx<double>>(int, const void*, int64_t, int64_t, const void*, int64_t,
@@ -953,9 +995,7 @@ int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_v
                      int64_t wstride_rhs, void* f, int64_t fstride_rhs, int64_t len, int nrhs, double* part,
                      double* out, hipStream_t st) {
   if (m > MAXDOT) return (int)hipErrorInvalidValue;
-  int nb = (int)((len + RED_THREADS - 1) / RED_THREADS);
-  if (nb > RED_PAIRS) nb = RED_PAIRS;
-  if (nb < 1) nb = 1;
+  const int nb = norm_blocks(len, out ? RED_PAIRS : FUSE_BLOCKS);
   const dim3 grd(nb, nrhs), blk(RED_THREADS);
   const TV* Vp = (const TV*)V;
   switch (m) {
@@ -966,7 +1006,7 @@ int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_v
     case 5: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 5>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
     default: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 0>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part);
   }
-  hipLaunchKernelGGL(k_reduce_parts, dim3(2, nrhs), dim3(256), 0, st, 2, nb, part, out);
+  if (out) hipLaunchKernelGGL(k_reduce_parts, dim3(2, nrhs), dim3(256), 0, st, 2, nb, part, out);
   return (int)hipGetLastError();
 }
 template int launch_axpy_norm<cx<double>, cx<float>>(int, const double*, const void*, int64_t, int64_t, void*,
@@ -989,9 +1029,14 @@ template int launch_axpy_norm<cx<float>, cx<float>>(int, const double*, const vo
 //   a2 = conj(<R1,V2>)/n2  (<V2 - b V1, r1> = <V2, r1> since r1 is orthogonal to V1),
 //   coef[s] = (a1 - a2 b, a2)  for  e = coef0 E1 + coef1 E2.
 // Zero denominators give zero coefficients.
-__global__ void k_kcycle_coef(int stage, const double* __restrict__ dots, double* __restrict__ coef,
-                              double* __restrict__ state, int nrhs) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_kcycle_coef(int stage, const double* __restrict__ dots_in,
+                                                      const double* __restrict__ part, int nb,
+                                                      double* __restrict__ coef, double* __restrict__ state,
+                                                      int nrhs) {
+  __shared__ double vals[FUSE_VALS];
+  const int m2 = stage == 1 ? 4 : 6;
+  const double* __restrict__ dots = small_reduction(nrhs * m2, m2, dots_in, part, nb, vals);
+  const int s = threadIdx.x;
   if (s >= nrhs) return;
   if (stage == 1) {
     const double d11 = dots[(s * 2 + 0) * 2];
@@ -1018,8 +1063,10 @@ __global__ void k_kcycle_coef(int stage, const double* __restrict__ dots, double
   }
 }
 
-int launch_kcycle_coef(int stage, const double* dots, double* coef, double* state, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_kcycle_coef, dim3((nrhs + 63) / 64), dim3(64), 0, st, stage, dots, coef, state, nrhs);
+int launch_kcycle_coef(int stage, const double* dots, const double* part, int nb, double* coef, double* state,
+                       int nrhs, hipStream_t st) {
+  if (nrhs < 1 || nrhs > 256 || (part && nrhs * (stage == 1 ? 4 : 6) > FUSE_VALS)) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_kcycle_coef, dim3(1), dim3(256), 0, st, stage, dots, part, nb, coef, state, nrhs);
   return (int)hipGetLastError();
 }
 
@@ -1076,8 +1123,11 @@ __device__ inline zc* gm_sn(double* st, int s) { return gm_g(st, s) + MAXDOT; }
 __device__ inline double* gm_cs(double* st, int s) { return (double*)(gm_sn(st, s) + MAXDOT); }
 
 // start of a restart cycle: beta = ||r||, g = (beta, 0, ...), scale = 1/beta
-__global__ void k_gm_start(int nrhs, const double* __restrict__ nrm2, double* __restrict__ st,
-                           double* __restrict__ scale) {
+__global__ void __launch_bounds__(256) k_gm_start(int nrhs, const double* __restrict__ nrm2_in,
+                                                   const double* __restrict__ part, int nb,
+                                                   double* __restrict__ st, double* __restrict__ scale) {
+  __shared__ double vals[FUSE_VALS];
+  const double* __restrict__ nrm2 = small_reduction(nrhs * 2, 2, nrm2_in, part, nb, vals);
   int s = threadIdx.x;
   if (s >= nrhs) return;
   double beta = sqrt(nrm2[2 * s]);
@@ -1089,8 +1139,11 @@ __global__ void k_gm_start(int nrhs, const double* __restrict__ nrm2, double* __
 }
 
 // after the dots h_i = <V_i, w>, i <= j: store column j and coef = -h
-__global__ void k_gm_hcol(int nrhs, int j, const double* __restrict__ dots, double* __restrict__ st,
-                          double* __restrict__ coef) {
+__global__ void __launch_bounds__(256) k_gm_hcol(int nrhs, int j, const double* __restrict__ dots_in,
+                                                  const double* __restrict__ part, int nb,
+                                                  double* __restrict__ st, double* __restrict__ coef) {
+  __shared__ double vals[FUSE_VALS];
+  const double* __restrict__ dots = small_reduction(nrhs * 2 * (j + 1), 2 * (j + 1), dots_in, part, nb, vals);
   int s = threadIdx.x;
   if (s >= nrhs) return;
   for (int i = 0; i <= j; ++i) {
@@ -1103,8 +1156,11 @@ __global__ void k_gm_hcol(int nrhs, int j, const double* __restrict__ dots, doub
 
 // after ||w||^2: subdiagonal, previous rotations, new rotation, g update,
 // scale = 1/h_{j+1,j}
-__global__ void k_gm_rotate(int nrhs, int j, const double* __restrict__ nrm2, double* __restrict__ st,
-                            double* __restrict__ scale) {
+__global__ void __launch_bounds__(256) k_gm_rotate(int nrhs, int j, const double* __restrict__ nrm2_in,
+                                                    const double* __restrict__ part, int nb,
+                                                    double* __restrict__ st, double* __restrict__ scale) {
+  __shared__ double vals[FUSE_VALS];
+  const double* __restrict__ nrm2 = small_reduction(nrhs * 2, 2, nrm2_in, part, nb, vals);
   int s = threadIdx.x;
   if (s >= nrhs) return;
   double hn = sqrt(nrm2[2 * s]);
@@ -1170,16 +1226,22 @@ __global__ void k_gm_backsolve(int nrhs, int k, const double* __restrict__ st, d
   }
 }
 
-int launch_gm_start(int nrhs, const double* nrm2, double* st, double* scale, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_start, dim3(1), dim3(64), 0, s, nrhs, nrm2, st, scale);
+int launch_gm_start(int nrhs, const double* nrm2, const double* part, int nb, double* st, double* scale,
+                    hipStream_t s) {
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 > FUSE_VALS)) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gm_start, dim3(1), dim3(256), 0, s, nrhs, nrm2, part, nb, st, scale);
   return (int)hipGetLastError();
 }
-int launch_gm_hcol(int nrhs, int j, const double* dots, double* st, double* coef, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_hcol, dim3(1), dim3(64), 0, s, nrhs, j, dots, st, coef);
+int launch_gm_hcol(int nrhs, int j, const double* dots, const double* part, int nb, double* st, double* coef,
+                   hipStream_t s) {
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 * (j + 1) > FUSE_VALS)) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gm_hcol, dim3(1), dim3(256), 0, s, nrhs, j, dots, part, nb, st, coef);
   return (int)hipGetLastError();
 }
-int launch_gm_rotate(int nrhs, int j, const double* nrm2, double* st, double* scale, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_rotate, dim3(1), dim3(64), 0, s, nrhs, j, nrm2, st, scale);
+int launch_gm_rotate(int nrhs, int j, const double* nrm2, const double* part, int nb, double* st, double* scale,
+                     hipStream_t s) {
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 > FUSE_VALS)) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gm_rotate, dim3(1), dim3(256), 0, s, nrhs, j, nrm2, part, nb, st, scale);
   return (int)hipGetLastError();
 }
 int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStream_t s) {
