@@ -493,47 +493,54 @@ __global__ void __launch_bounds__(256) k_prolong_add(LevelArgs<T> F, LevelArgs<T
   }
 }
 
-// 3D prolongation-add with fixed 2x2x2 coarse stencils: every axis takes two
+// 3D prolongation-add with fixed coarse stencils: x_2 and x_3 take two
 // coarse indices (clamped to the coarse grid) and weights that are zero
 // where the variable-length stencil of k_prolong_add has no term, so the
-// loop nest has no data-dependent trip counts.  Same weights as
-// k_prolong_add: linear along the face normal (coincident fine faces take
-// the coarse face, odd faces the mean of the two beside them, boundary
-// coarse faces contribute zero), 3/4 - 1/4 across cells.
+// loop nest has no data-dependent trip counts; x_1 takes the three coarse
+// indices a pair of fine cells needs.  Same weights as k_prolong_add: linear
+// along the face normal (coincident fine faces take the coarse face, odd
+// faces the mean of the two beside them, boundary coarse faces contribute
+// zero), 3/4 - 1/4 across cells.
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong3(LevelArgs<T> F, LevelArgs<T> C, const cx<T>* __restrict__ e,
                                                    cx<T>* __restrict__ x, int nrhs) {
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  // One thread per pair of fine cells (2I, 2I+1) along x_1 (fine n_1 is
+  // even on every level that prolongs): both share the coarse x_1
+  // neighbourhood I-1, I, I+1.  Weights are exact dyadic fractions and the
+  // terms are added in the same order as one cell at a time would.
+  const int hp = F.n[0] >> 1;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  if (cell >= F.fs || s >= nrhs) return;
+  if (id >= hp * F.n[1] * F.n[2] || s >= nrhs) return;
+  const int I = id % hp;
+  const int t = id / hp;
   int i[3];
-  i[0] = cell % F.n[0];
-  const int t = cell / F.n[0];
+  i[0] = 2 * I;
   i[1] = t % F.n[1];
   i[2] = t / F.n[1];
   const int cs[3] = {1, C.n[0], C.n[0] * C.n[1]};
-  // per axis: coarse offsets and weights of the cell stencil (c) and of the
-  // face-normal stencil (f)
+  // axes x_2, x_3: coarse offsets and weights of the cell stencil (c) and of
+  // the face-normal stencil (f)
   int oc[3][2], of[3][2];
   T wc[3][2], wf[3][2];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int I = i[a] >> 1;
-    const int I2 = (i[a] & 1) ? I + 1 : I - 1;
+  for (int a = 1; a < 3; ++a) {
+    const int Ia = i[a] >> 1;
+    const int I2 = (i[a] & 1) ? Ia + 1 : Ia - 1;
     const bool ok2 = I2 >= 0 && I2 < C.n[a];
-    oc[a][0] = I * cs[a];
-    oc[a][1] = (ok2 ? I2 : I) * cs[a];
+    oc[a][0] = Ia * cs[a];
+    oc[a][1] = (ok2 ? I2 : Ia) * cs[a];
     wc[a][0] = T(0.75);
     wc[a][1] = ok2 ? T(0.25) : T(0);
     int J0, J1;
     T v0, v1;
     if ((i[a] & 1) == 0) {
-      J0 = J1 = I;
+      J0 = J1 = Ia;
       v0 = T(1);
       v1 = T(0);
     } else {
-      J0 = I;
-      J1 = I + 1;
+      J0 = Ia;
+      J1 = Ia + 1;
       v0 = v1 = T(0.5);
     }
     const bool ok0 = J0 >= 1 && J0 <= C.n[a] - 1, ok1 = J1 >= 1 && J1 <= C.n[a] - 1;
@@ -542,26 +549,42 @@ __global__ void __launch_bounds__(256) k_prolong3(LevelArgs<T> F, LevelArgs<T> C
     wf[a][0] = ok0 ? v0 : T(0);
     wf[a][1] = ok1 ? v1 : T(0);
   }
+  // axis x_1, cell stencil: even cell 0.75 e[I] + 0.25 e[I-1], odd cell
+  // 0.75 e[I] + 0.25 e[I+1]; face stencil: even face 2I takes e[I], odd face
+  // 2I+1 takes (e[I] + e[I+1]) / 2 (coarse faces 0 and n_1 are not unknowns)
+  const int Im = I > 0 ? I - 1 : I, Ip = I + 1 < C.n[0] ? I + 1 : I;
+  const T wm = I > 0 ? T(0.25) : T(0), wp = I + 1 < C.n[0] ? T(0.25) : T(0);
+  const T fe = I >= 1 ? T(1) : T(0), fo0 = I >= 1 ? T(0.5) : T(0), fo1 = I + 1 <= C.n[0] - 1 ? T(0.5) : T(0);
+  const int64_t cell = ((int64_t)i[2] * F.n[1] + i[1]) * F.n[0] + i[0];
   const cx<T>* es = e + s * C.vs;
   cx<T>* xs = x + s * F.vs;
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    if (f < 3 && i[f] == 0) continue;  // boundary face stays zero
+    if ((f == 1 && i[1] == 0) || (f == 2 && i[2] == 0)) continue;  // boundary faces stay zero
     const cx<T>* ef = es + (int64_t)f * C.fs;
-    cx<T> acc = czero<T>();
+    cx<T> ae = czero<T>(), ao = czero<T>();
 #pragma unroll
     for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
-      for (int a1 = 0; a1 < 2; ++a1)
-#pragma unroll
-        for (int a0 = 0; a0 < 2; ++a0) {
-          const int o = (f == 0 ? of[0][a0] : oc[0][a0]) + (f == 1 ? of[1][a1] : oc[1][a1]) +
-                        (f == 2 ? of[2][a2] : oc[2][a2]);
-          const T wgt = (f == 0 ? wf[0][a0] : wc[0][a0]) * (f == 1 ? wf[1][a1] : wc[1][a1]) *
-                        (f == 2 ? wf[2][a2] : wc[2][a2]);
-          acc += wgt * ef[o];
+      for (int a1 = 0; a1 < 2; ++a1) {
+        const int o = (f == 1 ? of[1][a1] : oc[1][a1]) + (f == 2 ? of[2][a2] : oc[2][a2]);
+        const T w12 = (f == 1 ? wf[1][a1] : wc[1][a1]) * (f == 2 ? wf[2][a2] : wc[2][a2]);
+        const cx<T> eI = ef[o + I], eP = ef[o + Ip];
+        if (f == 0) {
+          ae += (fe * w12) * eI;
+          ao += (fo0 * w12) * eI;
+          ao += (fo1 * w12) * eP;
+        } else {
+          const cx<T> eM = ef[o + Im];
+          ae += (T(0.75) * w12) * eI;
+          ae += (wm * w12) * eM;
+          ao += (T(0.75) * w12) * eI;
+          ao += (wp * w12) * eP;
         }
-    xs[(int64_t)f * F.fs + cell] += acc;
+      }
+    cx<T>* xf = xs + (int64_t)f * F.fs + cell;
+    if (f != 0 || I != 0) xf[0] += ae;  // fine face 0 along x_1 is not an unknown
+    xf[1] += ao;
   }
 }
 
@@ -579,8 +602,9 @@ template <typename T>
 int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* e, void* x, int nrhs,
                        hipStream_t st) {
   dim3 blk(256), grd((unsigned)((F.fs + 255) / 256), nrhs);
-  if (dim == 3 && F.fs <= 0x7fffffffll)
-    hipLaunchKernelGGL((k_prolong3<T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
+  if (dim == 3 && F.fs <= 0x7fffffffll && (F.n[0] & 1) == 0 && F.n[0] == 2 * C.n[0])
+    hipLaunchKernelGGL((k_prolong3<T>), dim3((unsigned)((F.fs / 2 + 255) / 256), nrhs), blk, 0, st, F, C,
+                       (const cx<T>*)e, (cx<T>*)x, nrhs);
   else if (dim == 3)
     hipLaunchKernelGGL((k_prolong_add<3, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
   else

@@ -131,7 +131,7 @@ def test_restrict_residual(shape, adjoint):
     assert _maxrel(rc0, ref0) <= 1e-14
 
 
-@pytest.mark.parametrize("shape", [(8, 12, 16), (12, 20)])
+@pytest.mark.parametrize("shape", [(8, 12, 16), (6, 10, 14), (12, 20)])
 def test_prolong_add(shape):
     P = _params(shape, levels=2)
     prob = _gpu_problem(P, shape)
