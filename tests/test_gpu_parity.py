@@ -210,6 +210,27 @@ def test_kcycle_f64(shape, levels, coarse, adjoint):
     assert _relerr(x, ref) <= 1e-10
 
 
+@pytest.mark.parametrize("nrhs", [1, 3, 9])
+def test_kcycle_reductions_any_batch(nrhs):
+    """the K-cycle coefficients and the coarsest GMRES finish reductions of
+    at most 16 values inside their bookkeeping kernels and larger ones in a
+    separate pass: with 1 right-hand side every reduction takes the first
+    path, with 3 both occur (GMRES columns from the third on, the second
+    K-cycle stage), with 9 only the second; every column equals the
+    oracle's K-cycle"""
+    shape = (8, 12, 16)
+    P = _params(shape, levels=3, coarse="krylov")
+    prob = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6, cycle="K")
+    lv = _oracle_levels(P, shape)[0]
+    cp = C.CycleParams(levels=3, alpha=P["alpha"], damping=P["damping"], coarse="krylov", coarse_sweeps=2,
+                       coarse_restart=5, coarse_maxit=6, coarse_rtol=0.0, calls=3)
+    hier = C.Hierarchy(lv, cp)
+    b = random_field(shape, 19, nrhs=nrhs)
+    x = _host(prob.vcycle(_dev(b)))
+    ref = np.stack([hier.vcycle_storage(b[s]) for s in range(nrhs)])
+    assert _relerr(x, ref) <= 1e-10
+
+
 def test_kcycle_mixed_precision_solve():
     """float32 K-cycle inside float64 FGMRES: converges and agrees with the
     float64 direct solution to 1e-5"""
