@@ -333,6 +333,33 @@ def test_solve_batched_rhs_independent():
         assert infob[s]["relres"] <= 1e-8
 
 
+def test_solve_degenerate_right_hand_sides():
+    """a zero right-hand side has the zero solution, reported converged with
+    no iterations, beside a live one in the same batch; an all-zero batch
+    launches no iteration; the largest batch (64 right-hand sides) solves
+    every column; one more is rejected before anything runs"""
+    from paper_2307_03242_amd._lib import ElhError
+    shape = (8, 8, 8)
+    P = _params(shape, levels=2, coarse="relax")
+    prob = _gpu_problem(P, shape, coarse_sweeps=4)
+    q = np.stack([np.zeros((4,) + shape, dtype=np.complex128), point_source(shape)])
+    u, info, code = prob.solve(_dev(q), rtol=1e-8, maxit=300)
+    uh = _host(u)
+    assert code == 0 and info[0]["status"] == 0 and info[0]["iters"] == 0 and info[0]["relres"] == 0.0
+    assert np.all(uh[0] == 0)
+    assert info[1]["status"] == 0 and info[1]["relres"] <= 1e-8
+    u0, info0, code0 = prob.solve(_dev(q[:1]), rtol=1e-8, maxit=300)
+    assert code0 == 0 and info0[0]["iters"] == 0 and np.all(_host(u0) == 0)
+    q64 = random_field(shape, 50, nrhs=64)
+    u64, info64, code64 = prob.solve(_dev(q64), rtol=1e-6, maxit=300)
+    assert code64 == 0 and all(i["status"] == 0 and i["relres"] <= 1e-6 for i in info64)
+    r = prob.residual(_dev(q64), u64)
+    rel = torch.linalg.vector_norm(r.reshape(64, -1), dim=1) / torch.linalg.vector_norm(_dev(q64).reshape(64, -1), dim=1)
+    assert float(rel.max()) <= 1e-6 * (1 + 1e-6)
+    with pytest.raises(ElhError):
+        prob.solve(torch.zeros((65, 4) + shape, dtype=torch.complex128, device="cuda"))
+
+
 def test_argument_errors_on_gpu():
     shape = (8, 8, 8)
     P = _params(shape, levels=2)
