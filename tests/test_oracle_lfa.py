@@ -236,3 +236,13 @@ def test_lfa_reproduces_figures_3_and_4():
     p23, p1 = gold["fig4b_ppw_min"][0]
     assert _ppw_lfa(2 / 3, 0.7, 0.1, p23).rho_loc(step=0.05) < 1 < _ppw_lfa(2 / 3, 0.7, 0.1, p23 - 0.5).rho_loc(step=0.05)
     assert _ppw_lfa(1.0, 0.7, 0.1, p1).rho_loc(step=0.05) < 1 < _ppw_lfa(1.0, 0.7, 0.1, p1 - 1).rho_loc(step=0.05)
+
+
+def test_lfa_tables_script_runs(capsys):
+    """the script that prints the paper's LFA numbers (and the 3D tuning
+    table) runs end to end; a coarse sampling step keeps it short"""
+    from oracle import lfa_tables
+    lfa_tables.main(0.3)
+    out = capsys.readouterr().out
+    assert "Table 1" in out and "Figure 3(a)" in out and "Figure 4(b)" in out
+    assert len([l for l in out.splitlines() if "(0.37)" in l or "(0.73)" in l]) == 2
