@@ -9,7 +9,10 @@ Test infrastructure (see the package header).
   of lam, mu, rho; the absorbing layer keeps its physical width.
 * Cycle: Algorithm 1 (two-grid cycle) applied recursively with one
   recursive call (V-cycle) or two (W-cycle: the second call solves for the
-  residual left by the first, Section 2.2), or two calls used as the
+  residual left by the first, Section 2.2; on every level, so above the
+  coarsest level the coarse problem gets two coarsest solves, the second on
+  the residual of the first -- with an inexact coarsest solve that second
+  solve is not a no-op), or two calls used as the
   preconditioners of two steps of a Krylov method on the coarse system
   (K-cycle, Section 2.2; reading: flexible GCR, i.e. the coarse correction
   minimises the coarse residual over the span of the two preconditioned
@@ -158,7 +161,9 @@ class Hierarchy:
         r = b - self.A[l] @ x
         rc = self.R[l] @ r
         e = self.vcycle(rc, l + 1)
-        if self.p.calls == 2 and l + 1 < len(self.levels) - 1:
+        if self.p.calls == 2:
+            # second recursive call on the residual the first one leaves;
+            # above the coarsest level both calls are coarsest solves
             e = e + self.vcycle(rc - self.A[l + 1] @ e, l + 1)
         elif self.p.calls == 3:
             e = self.krylov_correction(rc, e, l + 1)

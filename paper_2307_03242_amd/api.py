@@ -238,7 +238,7 @@ class Problem:
         if q.dtype != torch.complex128:
             raise TypeError("right-hand sides must be complex128")
         nrhs = self._vec(q, 0)
-        u = torch.empty_like(q) if out is None else out
+        u = torch.empty_like(q) if out is None else self._same(out, q, "out")
         opts = L.SolveOpts(restart, maxit, rtol)
         stats = (L.SolveStats * nrhs)()
         hist = [(ctypes.c_double * maxit)() for _ in range(nrhs)]
@@ -288,7 +288,10 @@ class Problem:
         return us, infos, code
 
     def gradient(self, u, v):
+        if u.dtype != torch.complex128:
+            raise TypeError("forward fields must be complex128")
         nrhs = self._vec(u, 0)
+        self._same(v, u, "v")
         g = [torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(3)]
         L.check(self.lib.elh_gradient(self.handle, nrhs, _ptr(u), _ptr(v), _ptr(g[0]), _ptr(g[1]), _ptr(g[2])))
         return tuple(g)

@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libelh.so")
-SOURCES = ["elh_kernels.hip", "elh_stencil3d.hip", "elh_stencil3d_wave.hip", "elh_kaczmarz.hip", "elh_host.hip"]
+SOURCES = ["elh_kernels.hip", "elh_stencil3d_wave.hip", "elh_kaczmarz.hip", "elh_host.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -129,9 +129,7 @@ struct elh_handle {
   int use_graphs = 1;                                      // ELH_GRAPHS=0 disables capture
   double* hdots = nullptr;  // pinned host mirror
   double* hcoef = nullptr;
-  int stencil = 0;          // ELH_STENCIL: 0 wavefront march (default), 1 LDS-tiled, 2 point-wise
-  int zchunk = 32;          // x_3 planes per workgroup of the tiled stencil (ELH_ZCHUNK)
-  int tile_y = 10;          // tile height (slots) of the float32 tiled stencil (ELH_TILE_Y: 6 or 10)
+  int zchunk = 32;          // default x_3 planes per workgroup of the wavefront march (ELH_ZCHUNK)
   // stencil autotuner: chosen x_3 chunk of the wavefront march per (level,
   // precision, input precision, residual, adjoint, nrhs); ELH_TUNE=0 keeps
   // the default heuristic,
@@ -258,13 +256,8 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
   elh_handle* H = new elh_handle();
   H->d = *desc;
   {
-    const char* e = getenv("ELH_STENCIL");
-    if (e && strcmp(e, "tiled") == 0) H->stencil = 1;
-    if (e && strcmp(e, "generic") == 0) H->stencil = 2;
     const char* z = getenv("ELH_ZCHUNK");  // > 0: default chunk (shortened on small grids); < 0: exactly -z
     if (z && atoi(z) != 0) H->zchunk = atoi(z);
-    const char* ty = getenv("ELH_TILE_Y");
-    if (ty && (atoi(ty) == 6 || atoi(ty) == 10)) H->tile_y = atoi(ty);
     const char* g = getenv("ELH_GRAPHS");
     if (g && strcmp(g, "0") == 0) H->use_graphs = 0;
     const char* tu = getenv("ELH_TUNE");
@@ -323,18 +316,9 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
   if (ensure(H->gstate, (size_t)MAXRHS_KRYLOV * GM_STRIDE * 8) ||
       ensure(H->gpart, (size_t)MAXRHS_KRYLOV * 512 * MAXDOT * 2 * 8) ||
       ensure(H->gdots, MAXRHS_KRYLOV * MAXDOT * 16) || ensure(H->gnrm, MAXRHS_KRYLOV * 16) ||
-      ensure(H->gcoef, MAXRHS_KRYLOV * MAXDOT * 16) || ensure(H->gscale, MAXRHS_KRYLOV * 16) ||
-      ensure(H->ones, MAXRHS_KRYLOV * 16)) {
+      ensure(H->gcoef, MAXRHS_KRYLOV * MAXDOT * 16) || ensure(H->gscale, MAXRHS_KRYLOV * 16)) {
     elh_destroy(H);
     return ELH_ERR_OOM;
-  }
-  {
-    std::vector<double> one(2 * MAXRHS_KRYLOV, 0.0);
-    for (int i = 0; i < MAXRHS_KRYLOV; ++i) one[2 * i] = 1.0;
-    if (hipMemcpy(H->ones.p, one.data(), one.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
-      elh_destroy(H);
-      return fail(ELH_ERR_HIP, "upload of constants failed");
-    }
   }
   if (hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking) != hipSuccess) {
     elh_destroy(H);
@@ -433,6 +417,14 @@ static int check_common(elh_handle* H, int level, int dtype, int nrhs) {
 }
 
 static int ensure_cycle_bufs(elh_handle* H, int prec, int nrhs) {
+  if (H->d.cycle_calls == 2 && H->ones.bytes < (size_t)nrhs * 16) {
+    // W-cycle: coefficient 1 per rhs for adding the second coarse correction
+    if (ensure(H->ones, (size_t)nrhs * 16)) return ELH_ERR_OOM;
+    std::vector<double> one(H->ones.bytes / 8, 0.0);
+    for (size_t i = 0; i < one.size(); i += 2) one[i] = 1.0;
+    if (hipMemcpy(H->ones.p, one.data(), one.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(ELH_ERR_HIP, "upload of the W-cycle coefficients failed");
+  }
   for (int l = 0; l < H->nlev; ++l) {
     LevelData& L = H->lv[l];
     size_t bytes = (size_t)nrhs * L.vs * csz(prec);
@@ -549,7 +541,7 @@ static int stencil_choice(elh_handle* H, int l, bool shifted, bool adj, const vo
 template <typename T>
 static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs) {
   const bool fits32 = H->lv[l].fs * (int64_t)sizeof(cx<T>) <= (int64_t)0x7fffffff;
-  if (H->d.dim == 3 && H->stencil == 0 && fits32 && H->lv[l].fs >= 16 * 16 * 16) {
+  if (H->d.dim == 3 && fits32 && H->lv[l].fs >= 16 * 16 * 16) {
     const int c = stencil_choice<T, T>(H, l, shifted, adj, x, b, y, nrhs);
     if (c == 0x7fffffff) {
       if (adj) return launch_apply3d_w3_adj<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
@@ -557,8 +549,6 @@ static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x,
     }
     return launch_choice<T, T>(H, l, shifted, adj, x, b, y, nrhs, c);
   }
-  if (H->d.dim == 3 && !adj && H->stencil == 1 && H->lv[l].fs >= 24 * 24 * 24)
-    return launch_apply3d_tiled<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->tile_y, H->st);
   return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);
 }
 
@@ -1373,8 +1363,10 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
                            H->st));
     CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
   }
-  if (H->d.cycle_calls == 2 && l + 1 < H->nlev - 1) {
-    // W-cycle: second coarse cycle on the coarse residual, added to the first
+  if (H->d.cycle_calls == 2) {
+    // W-cycle: second coarse cycle on the coarse residual, added to the
+    // first (on every level: above the coarsest level these are two
+    // coarsest solves, the second on the residual the first leaves)
     CHK(op_apply<T>(H, l + 1, true, adj, C.x[prec].p, C.b[prec].p, C.r[prec].p, nrhs));
     CHK((launch_scale_copy<cx<T>, cx<T>>(nullptr, C.r[prec].p, C.vs, C.b[prec].p, C.vs, C.vs, nrhs, H->st)));
     CHK((launch_scale_copy<cx<T>, cx<T>>(nullptr, C.x[prec].p, C.vs, L.r[prec].p, C.vs, C.vs, nrhs, H->st)));
@@ -1463,7 +1455,7 @@ extern "C" int elh_apply_f32in(elh_handle* H, int flags, int nrhs, const void* x
   if (flags & ELH_SHIFTED) return fail(ELH_ERR_ARG, "the outer operator is unshifted");
   const bool adj = flags & ELH_ADJOINT;
   const LevelData& L0 = H->lv[0];
-  const bool direct = H->d.dim == 3 && !adj && H->stencil == 0 && L0.fs >= 16 * 16 * 16 &&
+  const bool direct = H->d.dim == 3 && !adj && L0.fs >= 16 * 16 * 16 &&
                       L0.fs * 16 <= (int64_t)0x7fffffff;
   if (direct) {
     CHK(op_apply_f32in(H, adj, x, y, nrhs));
@@ -1564,10 +1556,22 @@ extern "C" int elh_kaczmarz(elh_handle* H, int flags, int dtype, int nrhs, int s
   return 0;
 }
 
+// The K-cycle and the Krylov / Kaczmarz coarsest solves keep per-rhs
+// coefficients and reductions in buffers of MAXRHS_KRYLOV entries.
+static int check_cycle_nrhs(const elh_handle* H, int nrhs) {
+  if (nrhs <= MAXRHS_KRYLOV) return 0;
+  if (H->d.cycle_calls == 3) return fail(ELH_ERR_ARG, "at most %d right-hand sides with the K-cycle", MAXRHS_KRYLOV);
+  if (H->nlev >= 1 && (H->d.coarse_mode == ELH_COARSE_KRYLOV || H->d.coarse_mode == ELH_COARSE_KACZMARZ))
+    return fail(ELH_ERR_ARG, "at most %d right-hand sides with the Krylov / Kaczmarz coarsest solve", MAXRHS_KRYLOV);
+  return 0;
+}
+
 extern "C" int elh_vcycle(elh_handle* H, int flags, int dtype, int nrhs, const void* b, void* x) {
   int rc = check_common(H, 0, dtype, nrhs);
   if (rc) return rc;
   if (!b || !x || b == x) return fail(ELH_ERR_ARG, "b and x must be distinct non-NULL pointers");
+  rc = check_cycle_nrhs(H, nrhs);
+  if (rc) return rc;
   const int prec = prec_of(dtype);
   if (ensure_cycle_bufs(H, prec, nrhs)) return ELH_ERR_OOM;
   bool adj = flags & ELH_ADJOINT;
@@ -1616,7 +1620,7 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
       auto fn = [&]() { return cycle<float>(H, 0, adj, v, z, nrhs); };
       return graphs_ok(H) ? run_graph(H, 1, adj, nrhs, v, z, fn) : fn();
     };
-    const bool direct = H->d.dim == 3 && !adj && H->stencil == 0 && L0.fs >= 16 * 16 * 16 &&
+    const bool direct = H->d.dim == 3 && !adj && L0.fs >= 16 * 16 * 16 &&
                         L0.fs * 16 <= (int64_t)0x7fffffff;
     if (!direct && ensure(ws.t, (size_t)nrhs * len * 16)) return ELH_ERR_OOM;
     auto AZ = [&](const void* zi, void* wo) {

@@ -35,9 +35,6 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
 template <typename T>
 int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
                           hipStream_t st);
-template <typename T>
-int launch_apply3d_tiled(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc, int ty,
-                         hipStream_t st);
 int launch_coarsen_media(int dim, const int* nf, const double* a, double* out, hipStream_t st);
 int launch_media_finish(int64_t n, const double* lam, const double* mu, const double* rho, double* kap, float* mu32,
                         float* rho32, float* kap32, hipStream_t st);

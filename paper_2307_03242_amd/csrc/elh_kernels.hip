@@ -1,7 +1,8 @@
 // Reference-structured gfx950 kernels: operator apply / residual (all
 // levels, 2D and 3D, forward and adjoint), red-black full Vanka, MAC
 // restriction and prolongation, media setup and Krylov vector operations.
-// The tuned 3D finest-level stencil kernels live in elh_stencil3d.hip.
+// The 3D wavefront-march stencil kernels (levels from 16^3) live in
+// elh_stencil3d_wave.hip.
 #include "elh_device.h"
 #include "elh_internal.h"
 
@@ -1089,7 +1090,8 @@ __global__ void __launch_bounds__(256) k_kcycle_coef(int stage, const double* __
 
 int launch_kcycle_coef(int stage, const double* dots, const double* part, int nb, double* coef, double* state,
                        int nrhs, hipStream_t st) {
-  if (nrhs < 1 || nrhs > 256 || (part && nrhs * (stage == 1 ? 4 : 6) > FUSE_VALS)) return (int)hipErrorInvalidValue;
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * (stage == 1 ? 4 : 6) > FUSE_VALS))
+    return (int)hipErrorInvalidValue;
   hipLaunchKernelGGL(k_kcycle_coef, dim3(1), dim3(256), 0, st, stage, dots, part, nb, coef, state, nrhs);
   return (int)hipGetLastError();
 }

@@ -75,3 +75,54 @@ def test_create_rejects_bad_arguments_without_gpu():
     d.n[0] = 8
     d.beta = 1.5
     assert lib.elh_create(ctypes.byref(d), dummy, dummy, dummy, None, ctypes.byref(h)) == _lib.ELH_ERR_ARG
+
+
+class _NoCallLib:
+    """stands in for libelh: any call into it fails the test"""
+
+    def __getattr__(self, name):
+        def call(*a, **k):
+            raise AssertionError("library entry point %s reached" % name)
+        return call
+
+
+def _cpu_problem():
+    """a Problem whose vectors may live on the host: the binding's argument
+    checks run without a GPU, and nothing reaches the library"""
+    import torch
+    from paper_2307_03242_amd.api import Problem
+
+    class HostProblem(Problem):
+        def _vec(self, t, level):
+            full = (self.dim + 1,) + self.shape
+            if tuple(t.shape) == full:
+                return 1
+            if t.dim() == len(full) + 1 and tuple(t.shape[1:]) == full:
+                return t.shape[0]
+            raise ValueError("shape")
+
+    p = object.__new__(HostProblem)
+    p.lib = _NoCallLib()
+    p.device = torch.device("cpu")
+    p.dim, p.shape, p.levels = 3, (4, 4, 4), 2
+    p.handle = ctypes.c_void_p(0)
+    return p
+
+
+def test_solve_and_gradient_check_their_buffers_without_gpu():
+    """a caller-supplied solution buffer and the adjoint fields of the
+    gradient must have the right-hand side's layout and dtype before any
+    library call (the library reads and writes nrhs full complex128
+    vectors through them)"""
+    import torch
+    p = _cpu_problem()
+    q = torch.zeros((2, 4, 4, 4, 4), dtype=torch.complex128)
+    for bad in (torch.zeros_like(q, dtype=torch.complex64), q[:1].clone(), torch.zeros(q.numel() // 2, dtype=q.dtype),
+                torch.zeros((2, 4, 4, 4, 8), dtype=q.dtype)[..., :4]):
+        with pytest.raises(ValueError):
+            p.solve(q, out=bad)
+    with pytest.raises(TypeError):
+        p.gradient(q.to(torch.complex64), q.to(torch.complex64))
+    for bad in (q.to(torch.complex64), q[:1].clone(), torch.zeros((2, 4, 4, 4, 8), dtype=q.dtype)[..., :4]):
+        with pytest.raises(ValueError):
+            p.gradient(q, bad)

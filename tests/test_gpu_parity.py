@@ -178,12 +178,15 @@ def test_vcycle_f64(shape, levels, coarse):
     assert _relerr(x, ref) <= 1e-11
 
 
-@pytest.mark.parametrize("shape,levels", [((16, 16, 24), 4), ((32, 48), 3)])
-def test_wcycle_f64(shape, levels):
-    P = _params(shape, levels=levels, coarse="krylov")
+@pytest.mark.parametrize("coarse", ["krylov", "relax"])
+@pytest.mark.parametrize("shape,levels", [((16, 16, 24), 4), ((16, 16, 16), 3), ((32, 48), 3)])
+def test_wcycle_f64(shape, levels, coarse):
+    """W-cycle: two recursive calls on every level (above the coarsest, two
+    coarsest solves, the second on the residual of the first)"""
+    P = _params(shape, levels=levels, coarse=coarse)
     prob = _gpu_problem(P, shape, coarse_sweeps=2, coarse_maxit=6, cycle="W")
     lv = _oracle_levels(P, shape)[0]
-    cp = C.CycleParams(levels=levels, alpha=P["alpha"], damping=P["damping"], coarse="krylov",
+    cp = C.CycleParams(levels=levels, alpha=P["alpha"], damping=P["damping"], coarse=coarse,
                        coarse_sweeps=2, coarse_restart=5, coarse_maxit=6, coarse_rtol=0.0, calls=2)
     hier = C.Hierarchy(lv, cp)
     b = random_field(shape, 17, nrhs=2)
@@ -381,6 +384,29 @@ def test_argument_errors_on_gpu():
         prob.relax(x[None].repeat(2, 1, 1, 1, 1).contiguous(), x, 0)
     with pytest.raises(ValueError):
         prob.prolong_add(x, x)  # e on the fine level instead of the coarse one
+
+
+def test_cycle_right_hand_side_limits():
+    """The K-cycle and the Krylov coarsest solve keep per-rhs state for at
+    most 64 right-hand sides: 65 are rejected before any launch.  The
+    W-cycle's own per-rhs coefficients grow with nrhs: 65 right-hand sides
+    with a sweep coarsest solve match the oracle column by column."""
+    from paper_2307_03242_amd._lib import ElhError
+    shape = (16, 16, 16)
+    b65 = random_field(shape, 60, nrhs=65)
+    for cyc, coarse in (("K", "relax"), ("W", "krylov"), ("V", "krylov")):
+        P = _params(shape, levels=3, coarse=coarse)
+        prob = _gpu_problem(P, shape, cycle=cyc)
+        with pytest.raises(ElhError) as ei:
+            prob.vcycle(_dev(b65))
+        assert ei.value.code == -1
+    P = _params(shape, levels=3, coarse="relax")
+    prob = _gpu_problem(P, shape, coarse_sweeps=2, cycle="W")
+    x = _host(prob.vcycle(_dev(b65)))
+    cp = C.CycleParams(levels=3, alpha=P["alpha"], damping=P["damping"], coarse="relax", coarse_sweeps=2, calls=2)
+    hier = C.Hierarchy(_oracle_levels(P, shape)[0], cp)
+    for s in (0, 37, 64):
+        assert _relerr(x[s], hier.vcycle_storage(b65[s])) <= 1e-11, s
 
 
 @pytest.mark.parametrize("precond", [torch.complex128, torch.complex64])

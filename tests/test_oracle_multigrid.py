@@ -242,6 +242,89 @@ def test_two_grid_is_linear_and_reduces_error():
     assert np.linalg.norm(e) < 0.5 ** 8 * n0
 
 
+def _half_sweep_error(A, dofs, colours, w, colour, e):
+    """error propagation of one damped red-black Vanka colour written out
+    from its definition: e <- e - w sum_c E_c A_cc^-1 E_c^T A e over the
+    cells c of that colour, A_cc the submatrix on the cell's unknowns."""
+    Ae = A @ e
+    out = e.copy()
+    for c in np.nonzero(colours == colour)[0]:
+        d = dofs[c][dofs[c] >= 0]
+        out[d] -= w * np.linalg.solve(A[np.ix_(d, d)].toarray(), Ae[d])
+    return out
+
+
+def _cycle_error_closed_form(hier, l, v, gamma, coarse_sweeps):
+    """E_l v from the recursion of Algorithm 1 with gamma recursive calls:
+    E_l = S^nu2 (I - P_l (I - E_{l+1}^gamma) A_{l+1}^-1 R_l A_l) S^nu1, and on
+    the coarsest level the coarse iteration's own error operator (sweeps
+    from zero: S_c^k; exact solve: 0)."""
+    p = hier.p
+    last = len(hier.levels) - 1
+    A = hier.A[l]
+    dofs = cell_dofs(hier.levels[l])
+    cols = (np.indices(hier.levels[l].np_shape).reshape(hier.levels[l].dim, -1).sum(axis=0)) % 2
+
+    def sweep(e, w):
+        return _half_sweep_error(A, dofs, cols, w, 1, _half_sweep_error(A, dofs, cols, w, 0, e))
+
+    if l == last:
+        if p.coarse == "direct":
+            return np.zeros_like(v)
+        for _ in range(coarse_sweeps):
+            v = sweep(v, p.wc())
+        return v
+    w = p.w(l)
+    for _ in range(p.nu1):
+        v = sweep(v, w)
+    y = spla.spsolve(hier.A[l + 1].tocsc(), hier.R[l] @ (A @ v))
+    z = y
+    for _ in range(gamma):
+        z = _cycle_error_closed_form(hier, l + 1, z, gamma, coarse_sweeps)
+    v = v - hier.P[l] @ (y - z)
+    for _ in range(p.nu2):
+        v = sweep(v, w)
+    return v
+
+
+@pytest.mark.parametrize("shape,levels,calls,coarse,adjoint", [
+    ((16, 16), 3, 2, "relax", False),
+    ((16, 16), 4, 2, "relax", False),
+    ((16, 16), 3, 1, "relax", False),
+    ((16, 16), 4, 1, "relax", False),
+    ((16, 16), 3, 2, "direct", False),
+    ((16, 16), 3, 2, "relax", True),
+    ((8, 8, 8), 3, 2, "relax", False),
+])
+def test_cycle_error_operator_matches_recursion(shape, levels, calls, coarse, adjoint):
+    """Pin of the multilevel recursion (Section 2.2: Algorithm 1 applied
+    recursively with one call for V, two for W).  The cycle's error operator
+    E = I - M A, taken from the oracle's cycle on random vectors, equals the
+    closed-form recursion built from the level operators, the transfers, a
+    sparse direct coarse solve and the smoother's error operator written out
+    from its definition.  A coarsest solve by k sweeps is inexact, so the
+    W-cycle's second coarse call on the level above the coarsest is visible
+    (E_c^2 != E_c): dropping it, or giving it the wrong residual, fails."""
+    m = make_media(shape, 4)
+    lv = _level(shape, omega=omega_for_ppw(m["vs"].min(), 1.0, 10), media=m, abl=(3.0, 2.0))
+    k = 3
+    cp = C.CycleParams(levels=levels, alpha=0.3, damping=(0.55, 0.35, 0.25, 0.25), coarse=coarse,
+                       coarse_sweeps=k, calls=calls)
+    hier = C.Hierarchy(lv, cp, adjoint=adjoint)
+    rng = np.random.default_rng(11)
+    A0 = hier.A[0]
+    for _ in range(3):
+        v = rng.standard_normal(A0.shape[0]) + 1j * rng.standard_normal(A0.shape[0])
+        e_cycle = v - hier.vcycle(A0 @ v)
+        e_closed = _cycle_error_closed_form(hier, 0, v, calls, k)
+        assert np.linalg.norm(e_cycle - e_closed) <= 1e-11 * np.linalg.norm(v)
+    if calls == 2 and coarse == "relax":
+        # the second coarse call changes the result: a V-cycle recursion
+        # (gamma = 1) on the same hierarchy does not match
+        e_v = _cycle_error_closed_form(hier, 0, v, 1, k)
+        assert np.linalg.norm(e_cycle - e_v) > 1e-6 * np.linalg.norm(v)
+
+
 def test_kcycle_with_exact_coarse_solve_is_the_two_grid_cycle():
     """K-cycle pin 1: with an exact coarse solve the first preconditioned
     direction already solves the coarse system, so the second Krylov step
