@@ -78,8 +78,10 @@ typedef struct {
                            2^(levels-1)                                       */
   double h;             /* grid spacing of level 0                            */
   double omega;         /* angular frequency (eq. elasticHelm)                */
-  double gamma;         /* physical attenuation (eq. elasticHelm)             */
-  double alpha;         /* preconditioner shift added to gamma (eq. shift)    */
+  double gamma;         /* physical attenuation (eq. elasticHelm), >= 0       */
+  double alpha;         /* preconditioner shift added to gamma (eq. shift),
+                           >= 0; gamma + alpha > 0 keeps the shifted operator
+                           nonsingular (elh_create: ELH_ERR_ARG otherwise)    */
   double beta;          /* spread weight of the compact stencils, (0,1];
                            2/3 is the LFA-tuned value (Section 4.3)           */
   double abl_width;     /* absorbing-layer width, PHYSICAL units (0 = none)   */
@@ -118,6 +120,19 @@ typedef struct {
   int restart;          /* FGMRES restart length m (paper: 5)                 */
   int maxit;            /* maximum preconditioner applications                */
   double rtol;          /* stop at ||q - H u|| <= rtol ||q|| (per RHS)        */
+  int zero_x0;          /* 1: start from u = 0 (the paper's choice, Section
+                           5); 0: u holds the initial guess on entry, e.g.
+                           the iterate an earlier call returned with
+                           ELH_NOT_CONVERGED (resume).  The stop stays
+                           relative to ||q||, and a resumed solve continues
+                           the iterates of the interrupted one exactly when
+                           it was cut at a restart boundary (maxit a
+                           multiple of restart)                               */
+  int store_z_fp32;     /* with precond_dtype ELH_C64: 1 keeps the
+                           preconditioned vectors z_j in complex64 (exact,
+                           since the cycle produces them in float32; half
+                           the memory and traffic), 0 widens them to
+                           complex128; must be 0 with ELH_C128            */
 } elh_solve_opts;
 
 typedef struct {        /* (host) one record per right-hand side              */
@@ -223,8 +238,14 @@ int elh_vcycle(elh_handle* h, int flags, int dtype, int nrhs, const void* b,
 
 /* Solve H u = q for nrhs right-hand sides (float64 q, u on level 0) by
  * FGMRES(opts->restart) right-preconditioned with the cycle in
- * desc->precond_dtype.  u is overwritten (zero initial guess).  stats:
- * (host) array of nrhs records, may be NULL. */
+ * desc->precond_dtype (Section 5: restarted flexible GMRES, relative-
+ * residual stop).  u is overwritten; it is read first as the initial guess
+ * when opts->zero_x0 == 0.  stats: (host) array of nrhs records, may be
+ * NULL.  Returns ELH_OK when every right-hand side met rtol,
+ * ELH_NOT_CONVERGED when one did not within maxit (u then holds the last
+ * iterate and the stats its true residual: a later call with zero_x0 = 0
+ * resumes from it), ELH_ERR_NUMERIC on a NaN/Inf norm (e.g. non-finite
+ * media or right-hand side), ELH_ERR_ARG on invalid options. */
 int elh_solve(elh_handle* h, int nrhs, const void* q, void* u,
               const elh_solve_opts* opts, elh_solve_stats* stats);
 

@@ -37,7 +37,8 @@ class Desc(ctypes.Structure):
 
 
 class SolveOpts(ctypes.Structure):
-    _fields_ = [("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("rtol", ctypes.c_double)]
+    _fields_ = [("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("zero_x0", ctypes.c_int), ("store_z_fp32", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):

@@ -234,12 +234,21 @@ class Problem:
         return x
 
     # -- solves ---------------------------------------------------------------
-    def _solve(self, fn, q, restart, maxit, rtol, out):
+    def _opts(self, restart, maxit, rtol, x0, store_z_fp32):
+        if store_z_fp32 is None:
+            store_z_fp32 = self.desc.precond_dtype == L.ELH_C64
+        return L.SolveOpts(restart, maxit, rtol, 0 if x0 else 1, 1 if store_z_fp32 else 0)
+
+    def _solve(self, fn, q, restart, maxit, rtol, out, x0=None, store_z_fp32=None):
         if q.dtype != torch.complex128:
             raise TypeError("right-hand sides must be complex128")
         nrhs = self._vec(q, 0)
         u = torch.empty_like(q) if out is None else self._same(out, q, "out")
-        opts = L.SolveOpts(restart, maxit, rtol)
+        if x0 is not None:
+            self._same(x0, q, "x0")
+            if x0.data_ptr() != u.data_ptr():
+                u.copy_(x0)
+        opts = self._opts(restart, maxit, rtol, x0 is not None, store_z_fp32)
         stats = (L.SolveStats * nrhs)()
         hist = [(ctypes.c_double * maxit)() for _ in range(nrhs)]
         for s, h in zip(stats, hist):
@@ -248,12 +257,16 @@ class Problem:
         code = L.check(fn(self.handle, nrhs, _ptr(q), _ptr(u), ctypes.byref(opts), stats))
         return u, [_info(s) for s in stats], code
 
-    def solve(self, q, restart=5, maxit=500, rtol=1e-6, out=None):
-        """u = H^{-1} q by preconditioned FGMRES; returns (u, info, code)."""
-        return self._solve(self.lib.elh_solve, q, restart, maxit, rtol, out)
+    def solve(self, q, restart=5, maxit=500, rtol=1e-6, out=None, x0=None, store_z_fp32=None):
+        """u = H^{-1} q by preconditioned FGMRES; returns (u, info, code).
+        x0: initial guess (default zero; e.g. the u of an earlier call that
+        returned code 1 to resume it; may be `out` itself).  store_z_fp32:
+        keep the preconditioned vectors in complex64 (default: with the
+        float32 cycle)."""
+        return self._solve(self.lib.elh_solve, q, restart, maxit, rtol, out, x0, store_z_fp32)
 
-    def solve_adjoint(self, r, restart=5, maxit=500, rtol=1e-6, out=None):
-        return self._solve(self.lib.elh_solve_adjoint, r, restart, maxit, rtol, out)
+    def solve_adjoint(self, r, restart=5, maxit=500, rtol=1e-6, out=None, x0=None, store_z_fp32=None):
+        return self._solve(self.lib.elh_solve_adjoint, r, restart, maxit, rtol, out, x0, store_z_fp32)
 
     @staticmethod
     def solve_batch(problems, qs, restart=5, maxit=500, rtol=1e-6):
@@ -274,7 +287,8 @@ class Problem:
         nrh = (ctypes.c_int * n)(*nr)
         qp = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
         up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
-        opts = L.SolveOpts(restart, maxit, rtol)
+        z32 = all(p.desc.precond_dtype == L.ELH_C64 for p in problems)
+        opts = L.SolveOpts(restart, maxit, rtol, 1, 1 if z32 else 0)
         stats = (L.SolveStats * sum(nr))()
         hist = [(ctypes.c_double * maxit)() for _ in range(sum(nr))]
         for s, h in zip(stats, hist):

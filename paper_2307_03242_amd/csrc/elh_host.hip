@@ -211,6 +211,9 @@ static int check_desc(const elh_desc* d) {
   if (d->coarse_restart + 1 > MAXDOT) return fail(ELH_ERR_ARG, "coarse_restart too large");
   if (d->precond_dtype != ELH_C64 && d->precond_dtype != ELH_C128) return fail(ELH_ERR_ARG, "bad precond_dtype");
   if (d->abl_width < 0) return fail(ELH_ERR_ARG, "abl_width must be >= 0");
+  if (!(d->gamma >= 0) || !(d->alpha >= 0) || !(d->gamma + d->alpha > 0))
+    return fail(ELH_ERR_ARG, "gamma and alpha must be >= 0 with gamma + alpha > 0");
+  if (!(d->omega > 0) || !isfinite(d->omega)) return fail(ELH_ERR_ARG, "omega must be positive and finite");
   return 0;
 }
 
@@ -244,7 +247,7 @@ static int build_dense(elh_handle* H);
 static int build_kaczmarz(elh_handle* H);
 
 static void tune_load(elh_handle* H);
-static int tune_key(int l, int prec, int iprec, bool resid, bool adj, int nrhs);
+static int tune_key(int l, int prec, int iprec, int kind, bool adj, int nrhs);
 
 extern "C" int elh_create(const elh_desc* desc, const double* lam, const double* mu, const double* rho,
                           void* stream, elh_handle** out) {
@@ -395,7 +398,8 @@ extern "C" int elh_stencil_choice(elh_handle* H, int level, int dtype, int flags
   if (dtype != ELH_C64 && dtype != ELH_C128) return fail(ELH_ERR_ARG, "dtype must be ELH_C64 or ELH_C128");
   if (!choice || nrhs < 1) return fail(ELH_ERR_ARG, "choice must be non-NULL and nrhs >= 1");
   const int prec = prec_of(dtype);
-  auto it = H->tuned.find(tune_key(level, prec, prec, residual != 0, (flags & ELH_ADJOINT) != 0, nrhs));
+  if (residual < 0 || residual > 2) return fail(ELH_ERR_ARG, "residual must be 0, 1 or 2");
+  auto it = H->tuned.find(tune_key(level, prec, prec, residual, (flags & ELH_ADJOINT) != 0, nrhs));
   *choice = it == H->tuned.end() ? -1 : it->second;
   return 0;
 }
@@ -444,8 +448,9 @@ static int ensure_cycle_bufs(elh_handle* H, int prec, int nrhs) {
 // ---------------------------------------------------------------------------
 static std::mutex g_tune_file_mu;
 
-static int tune_key(int l, int prec, int iprec, bool resid, bool adj, int nrhs) {
-  return (((((l * 2 + prec) * 2 + iprec) * 2 + (resid ? 1 : 0)) * 2 + (adj ? 1 : 0)) << 8) | (nrhs & 0xff);
+// kind: 0 apply, 1 residual, 2 residual restricted to the next level
+static int tune_key(int l, int prec, int iprec, int kind, bool adj, int nrhs) {
+  return (((((l * 2 + prec) * 2 + iprec) * 3 + kind) * 2 + (adj ? 1 : 0)) << 8) | (nrhs & 0xff);
 }
 
 // choices persisted by earlier processes for this handle's grids
@@ -458,18 +463,18 @@ static void tune_load(elh_handle* H) {
   while (fscanf(f, "%d %d %d %d %d %d %d %d %d", &n1, &n2, &n3, &prec, &iprec, &resid, &adj, &nrhs, &choice) == 9) {
     for (int l = 0; l < H->nlev; ++l)
       if (H->lv[l].n[0] == n1 && H->lv[l].n[1] == n2 && H->lv[l].n[2] == n3)
-        H->tuned[tune_key(l, prec, iprec, resid != 0, adj != 0, nrhs)] = choice;
+        if (resid >= 0 && resid <= 2) H->tuned[tune_key(l, prec, iprec, resid, adj != 0, nrhs)] = choice;
   }
   fclose(f);
 }
 
-static void tune_store(elh_handle* H, int l, int prec, int iprec, bool resid, bool adj, int nrhs, int choice) {
+static void tune_store(elh_handle* H, int l, int prec, int iprec, int kind, bool adj, int nrhs, int choice) {
   if (H->tune_path.empty()) return;
   std::lock_guard<std::mutex> lk(g_tune_file_mu);
   FILE* f = fopen(H->tune_path.c_str(), "a");
   if (!f) return;
-  fprintf(f, "%d %d %d %d %d %d %d %d %d\n", H->lv[l].n[0], H->lv[l].n[1], H->lv[l].n[2], prec, iprec,
-          resid ? 1 : 0, adj ? 1 : 0, nrhs, choice);
+  fprintf(f, "%d %d %d %d %d %d %d %d %d\n", H->lv[l].n[0], H->lv[l].n[1], H->lv[l].n[2], prec, iprec, kind,
+          adj ? 1 : 0, nrhs, choice);
   fclose(f);
 }
 
@@ -490,37 +495,38 @@ static int launch_choice(elh_handle* H, int l, bool shifted, bool adj, const voi
 
 // x_3 chunk for this call: the tuned choice if there is one; else,
 // when tuning is allowed here, time the candidates on the call's own
-// buffers (the operation is idempotent when y aliases neither x nor b) with
-// HIP events on the library's stream and keep the fastest.  The chunk only
-// changes which workgroup marches which planes, not any output's
+// buffers (the operation is idempotent when its output aliases no input)
+// with HIP events on the library's stream and keep the fastest.  The chunk
+// only changes which workgroup marches which planes, not any output's
 // arithmetic, so every choice gives bitwise the same result.  Never tunes
-// while the stream is being captured into a graph.
-template <typename T, typename TI>
-static int stencil_choice(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y,
-                          int nrhs) {
-  const int prec = sizeof(T) == 8 ? 0 : 1, iprec = sizeof(TI) == 8 ? 0 : 1;
-  const int key = tune_key(l, prec, iprec, b != nullptr, adj, nrhs);
+// while the stream is being captured into a graph.  n3: planes of the
+// marched column in the chunk's unit; launch(c) runs the kernel with chunk c.
+static constexpr int CHUNK_DEFAULT = 0x7fffffff;  // the launcher's heuristic
+
+template <typename Launch>
+static int tune_chunk(elh_handle* H, int l, int prec, int iprec, int kind, bool adj, int nrhs, int n3,
+                      bool may_tune, Launch launch) {
+  const int key = tune_key(l, prec, iprec, kind, adj, nrhs);
   auto it = H->tuned.find(key);
   if (it != H->tuned.end()) return it->second;
-  const int dflt = 0x7fffffff;  // the launcher's heuristic
-  if (!H->tune || nrhs > 255 || y == x || y == b) return dflt;
+  const int dflt = CHUNK_DEFAULT;
+  if (!H->tune || !may_tune || nrhs > 255) return dflt;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(H->st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return dflt;
   if (!H->tev[0]) {
     if (hipEventCreate(&H->tev[0]) != hipSuccess || hipEventCreate(&H->tev[1]) != hipSuccess) return dflt;
   }
-  const LevelData& L = H->lv[l];
   std::vector<int> cand;
   for (int zc : {1, 2, 4, 8, 16, 32, 64})
-    if (zc < L.n[2] && (zc >= 4 || L.n[2] <= 64)) cand.push_back(zc);  // 1, 2 only on short columns
-  if (L.n[2] <= 64) cand.push_back(L.n[2]);  // the whole column in one chunk
+    if (zc < n3 && (zc >= 4 || n3 <= 64)) cand.push_back(zc);  // 1, 2 only on short columns
+  if (n3 <= 64) cand.push_back(n3);  // the whole column in one chunk
   int best = dflt;
   float tbest = 0;
   for (int c : cand) {
-    if (launch_choice<T, TI>(H, l, shifted, adj, x, b, y, nrhs, c)) return dflt;  // warm-up
+    if (launch(c)) return dflt;  // warm-up
     if (hipEventRecord(H->tev[0], H->st) != hipSuccess) return dflt;
     for (int r = 0; r < 3; ++r)
-      if (launch_choice<T, TI>(H, l, shifted, adj, x, b, y, nrhs, c)) return dflt;
+      if (launch(c)) return dflt;
     if (hipEventRecord(H->tev[1], H->st) != hipSuccess) return dflt;
     float ms = 0;
     if (hipEventSynchronize(H->tev[1]) != hipSuccess || hipEventElapsedTime(&ms, H->tev[0], H->tev[1]) != hipSuccess)
@@ -531,19 +537,32 @@ static int stencil_choice(elh_handle* H, int l, bool shifted, bool adj, const vo
     }
   }
   H->tuned[key] = best;
-  tune_store(H, l, prec, iprec, b != nullptr, adj, nrhs, best);
+  tune_store(H, l, prec, iprec, kind, adj, nrhs, best);
   return best;
+}
+
+template <typename T, typename TI>
+static int stencil_choice(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y,
+                          int nrhs, bool may_tune = true) {
+  const int prec = sizeof(T) == 8 ? 0 : 1, iprec = sizeof(TI) == 8 ? 0 : 1;
+  return tune_chunk(H, l, prec, iprec, b != nullptr ? 1 : 0, adj, nrhs, H->lv[l].n[2],
+                    may_tune && y != x && y != b,
+                    [&](int c) { return launch_choice<T, TI>(H, l, shifted, adj, x, b, y, nrhs, c); });
 }
 
 // 3D levels from 16^3 whose fields fit 32-bit byte offsets take the
 // wavefront march (x_3 chunk from the autotuner); 2D and smaller levels the
 // point-wise kernel.
+static bool marches(const elh_handle* H, int l, size_t entry_bytes) {
+  return H->d.dim == 3 && H->lv[l].fs * (int64_t)entry_bytes <= (int64_t)0x7fffffff && H->lv[l].fs >= 16 * 16 * 16;
+}
+
 template <typename T>
-static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs) {
-  const bool fits32 = H->lv[l].fs * (int64_t)sizeof(cx<T>) <= (int64_t)0x7fffffff;
-  if (H->d.dim == 3 && fits32 && H->lv[l].fs >= 16 * 16 * 16) {
-    const int c = stencil_choice<T, T>(H, l, shifted, adj, x, b, y, nrhs);
-    if (c == 0x7fffffff) {
+static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x, const void* b, void* y, int nrhs,
+                    bool may_tune = true) {
+  if (marches(H, l, sizeof(cx<T>))) {
+    const int c = stencil_choice<T, T>(H, l, shifted, adj, x, b, y, nrhs, may_tune);
+    if (c == CHUNK_DEFAULT) {
       if (adj) return launch_apply3d_w3_adj<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
       return launch_apply3d_w3<T>(largs<T>(H, l, shifted), x, b, y, nrhs, H->zchunk, H->st);
     }
@@ -552,10 +571,32 @@ static int op_apply(elh_handle* H, int l, bool shifted, bool adj, const void* x,
   return launch_apply<T>(largs<T>(H, l, shifted), H->d.dim, adj, x, b, y, nrhs, H->st);
 }
 
+// rc = R (b - H_s x) from level l to l+1 (x == nullptr: x = 0, rc = R b):
+// one launch, the fine residual is never stored; the march form (x_3 chunk
+// in coarse planes from the autotuner) on march levels, the point-wise form
+// otherwise.
+template <typename T>
+static int op_restrict_residual(elh_handle* H, int l, bool adj, const void* x, const void* b, void* rc, int nrhs,
+                                bool may_tune = true) {
+  const LevelArgs<T> F = largs<T>(H, l, true), Cl = largs<T>(H, l + 1, true);
+  if (!x) return launch_restrict<T>(F, Cl, H->d.dim, b, rc, nrhs, H->st);
+  if (marches(H, l, sizeof(cx<T>))) {
+    const int prec = sizeof(T) == 8 ? 0 : 1;
+    const int c = tune_chunk(H, l, prec, prec, 2, adj, nrhs, H->lv[l + 1].n[2], may_tune && rc != x && rc != b,
+                             [&](int zc) {
+                               return launch_restrict_resid3d_w3<T>(F, Cl, adj, x, b, rc, nrhs, -zc, H->st);
+                             });
+    // default: half the fine default in coarse planes; ELH_ZCHUNK < 0 forces exactly -ELH_ZCHUNK coarse planes
+    const int dz = H->zchunk > 0 ? (H->zchunk / 2 > 0 ? H->zchunk / 2 : 1) : H->zchunk;
+    return launch_restrict_resid3d_w3<T>(F, Cl, adj, x, b, rc, nrhs, c == CHUNK_DEFAULT ? dz : -c, H->st);
+  }
+  return launch_restrict_resid<T>(F, Cl, H->d.dim, adj, x, b, rc, nrhs, H->st);
+}
+
 // outer operator on float32 input (level 0, float64 arithmetic and output)
 static int op_apply_f32in(elh_handle* H, bool adj, const void* x, void* y, int nrhs) {
   const int c = stencil_choice<double, float>(H, 0, false, adj, x, nullptr, y, nrhs);
-  if (c == 0x7fffffff || c == 0)
+  if (c == CHUNK_DEFAULT || c == 0)
     return launch_apply3d_w3<double, float>(largs<double>(H, 0, false), x, nullptr, y, nrhs, H->zchunk, H->st);
   return launch_choice<double, float>(H, 0, false, adj, x, nullptr, y, nrhs, c);
 }
@@ -672,9 +713,13 @@ static int scale_copy(elh_handle* H, const std::vector<zd>* a, const void* x, in
 // A Z_j is written straight into V_{j+1}; the Gram-Schmidt update, its
 // norm and (when TZ != T) the TZ copy that feeds the next preconditioner
 // application (cyc_in) come out of one pass.  No vector is rescaled.
+//
+// x0: x holds the initial guess (the first basis vector is the true
+// residual b - A x); otherwise x starts at zero and the first basis vector
+// is b.
 template <typename T, typename TZ, typename OpAZ, typename OpAR, typename OpM>
 static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, OpAR AR, OpM M, const void* b,
-                 void* x, int restart, int maxit, double rtol, GmresStats& st_out, void* cyc_in) {
+                 void* x, int restart, int maxit, double rtol, GmresStats& st_out, void* cyc_in, bool x0 = false) {
   typedef cx<T> CT;
   typedef cx<TZ> CZ;
   const bool cast_in = sizeof(TZ) != sizeof(T);
@@ -693,10 +738,18 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
   CHK(fetch_dots(H, nrhs, 1, dots));
   std::vector<double> nb(nrhs), beta(nrhs);
   for (int s = 0; s < nrhs; ++s) nb[s] = sqrt(dots[s].real());
-  // x = 0, V_0 = r = b
-  CHK(launch_zero(x, vbytes, st));
-  HIPCHK(hipMemcpyAsync(V, b, vbytes, hipMemcpyDeviceToDevice, st));
-  for (int s = 0; s < nrhs; ++s) beta[s] = nb[s];
+  if (x0) {
+    // V_0 = r = b - A x
+    CHK(AR((const void*)x, b, (void*)V));
+    CHK((launch_multidot<CT, CT>(1, V, 0, len, V, len, len, nrhs, (double*)H->part.p, (double*)H->dots.p, st)));
+    CHK(fetch_dots(H, nrhs, 1, dots));
+    for (int s = 0; s < nrhs; ++s) beta[s] = sqrt(dots[s].real());
+  } else {
+    // x = 0, V_0 = r = b
+    CHK(launch_zero(x, vbytes, st));
+    HIPCHK(hipMemcpyAsync(V, b, vbytes, hipMemcpyDeviceToDevice, st));
+    for (int s = 0; s < nrhs; ++s) beta[s] = nb[s];
+  }
   st_out.iters.assign(nrhs, 0);
   st_out.restarts.assign(nrhs, 0);
   st_out.status.assign(nrhs, ELH_NOT_CONVERGED);
@@ -706,12 +759,16 @@ static int gmres(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ AZ, Op
   std::vector<char> active(nrhs);
   int nact = 0;
   for (int s = 0; s < nrhs; ++s) {
+    if (!isfinite(nb[s]) || !isfinite(beta[s])) return fail(ELH_ERR_NUMERIC, "non-finite initial residual (rhs %d)", s);
     if (!(nb[s] > 0)) {
+      // q = 0: the solution is 0 (an initial guess is discarded)
       active[s] = 0;
-      st_out.status[s] = isfinite(nb[s]) ? ELH_OK : ELH_ERR_NUMERIC;
+      st_out.status[s] = ELH_OK;
       st_out.relres[s] = 0.0;
+      if (x0) CHK(launch_zero((CT*)x + (int64_t)s * len, len * (int64_t)sizeof(CT), st));
     } else {
-      active[s] = rtol < 1.0;
+      st_out.relres[s] = beta[s] / nb[s];
+      active[s] = st_out.relres[s] > rtol && beta[s] > 0;
       if (!active[s]) st_out.status[s] = ELH_OK;
     }
     nact += active[s];
@@ -1320,12 +1377,8 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
     zero = false;
     CHK(op_relax<T>(H, l, adj, 1, b, x, nrhs, false));
   }
-  // coarse right-hand side R (b - H_s x)
-  const void* r = b;
-  if (!zero) {
-    CHK(op_apply<T>(H, l, true, adj, x, b, L.r[prec].p, nrhs));
-    r = L.r[prec].p;
-  }
+  // coarse right-hand side R (b - H_s x), one fused launch
+  const void* xr = zero ? nullptr : x;
   if (H->d.cycle_calls == 3) {
     // K-cycle: the coarse correction from two steps of flexible GCR on the
     // coarse system, each preconditioned by the coarse cycle (or the
@@ -1341,7 +1394,7 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
     double* kc1 = kd + 6 * MAXRHS_KRYLOV;             // stage-1 coefficients: 2 per rhs
     double* kc2 = kc1 + 2 * MAXRHS_KRYLOV;            // stage-2 coefficients: 4 per rhs
     double* ks = kc2 + 4 * MAXRHS_KRYLOV;             // state: 4 per rhs
-    CHK(launch_restrict<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, r, R1, nrhs, H->st));
+    CHK(op_restrict_residual<T>(H, l, adj, xr, b, R1, nrhs));
     CHK(cycle<T>(H, l + 1, adj, R1, E1, nrhs));
     CHK(op_apply<T>(H, l + 1, true, adj, E1, nullptr, V1, nrhs));
     // the coefficient kernels finish small reductions themselves
@@ -1359,8 +1412,7 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
     CHK(launch_zero(C.x[prec].p, (int64_t)nrhs * C.vs * csz(prec), H->st));
     CHK((launch_multiaxpy<CT, CT>(2, kc2, E1, 4 * vec, C.vs, C.x[prec].p, C.vs, C.vs, nrhs, H->st)));
   } else {
-    CHK(launch_restrict<T>(largs<T>(H, l, true), largs<T>(H, l + 1, true), H->d.dim, r, C.b[prec].p, nrhs,
-                           H->st));
+    CHK(op_restrict_residual<T>(H, l, adj, xr, b, C.b[prec].p, nrhs));
     CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
   }
   if (H->d.cycle_calls == 2) {
@@ -1485,21 +1537,10 @@ extern "C" int elh_restrict_residual(elh_handle* H, int level, int flags, int dt
   if (rc) return rc;
   if (level >= H->nlev - 1) return fail(ELH_ERR_ARG, "no coarser level below %d", level);
   if (!b || !rc_out) return fail(ELH_ERR_ARG, "b and rc must be non-NULL");
-  const int prec = prec_of(dtype);
-  if (ensure_cycle_bufs(H, prec, nrhs)) return ELH_ERR_OOM;
   bool adj = flags & ELH_ADJOINT;
-  const void* r = b;
-  if (x) {
-    if (dtype == ELH_C128) CHK(op_apply<double>(H, level, true, adj, x, b, H->lv[level].r[prec].p, nrhs));
-    else CHK(op_apply<float>(H, level, true, adj, x, b, H->lv[level].r[prec].p, nrhs));
-    r = H->lv[level].r[prec].p;
-  }
-  if (dtype == ELH_C128)
-    CHK(launch_restrict<double>(largs<double>(H, level, true), largs<double>(H, level + 1, true), H->d.dim, r, rc_out,
-                                nrhs, H->st));
-  else
-    CHK(launch_restrict<float>(largs<float>(H, level, true), largs<float>(H, level + 1, true), H->d.dim, r, rc_out,
-                               nrhs, H->st));
+  if (rc_out == b || (x && rc_out == x)) return fail(ELH_ERR_ARG, "rc must not alias b or x");
+  if (dtype == ELH_C128) CHK(op_restrict_residual<double>(H, level, adj, x, b, rc_out, nrhs));
+  else CHK(op_restrict_residual<float>(H, level, adj, x, b, rc_out, nrhs));
   return 0;
 }
 
@@ -1592,6 +1633,12 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
   if (opts->restart < 1 || opts->restart + 1 > MAXDOT) return fail(ELH_ERR_ARG, "restart must be in 1..%d", MAXDOT - 1);
   if (opts->maxit < 1) return fail(ELH_ERR_ARG, "maxit must be >= 1");
   if (nrhs > MAXRHS_KRYLOV) return fail(ELH_ERR_ARG, "at most %d right-hand sides per solve", MAXRHS_KRYLOV);
+  if (!(opts->rtol >= 0)) return fail(ELH_ERR_ARG, "rtol must be >= 0");
+  if (opts->zero_x0 != 0 && opts->zero_x0 != 1) return fail(ELH_ERR_ARG, "zero_x0 must be 0 or 1");
+  if (opts->store_z_fp32 != 0 && opts->store_z_fp32 != 1) return fail(ELH_ERR_ARG, "store_z_fp32 must be 0 or 1");
+  if (opts->store_z_fp32 && H->d.precond_dtype != ELH_C64)
+    return fail(ELH_ERR_ARG, "store_z_fp32 needs the float32 cycle (precond_dtype ELH_C64)");
+  const bool x0 = opts->zero_x0 == 0;
   const int pprec = prec_of(H->d.precond_dtype);
   if (ensure_cycle_bufs(H, pprec, nrhs)) return ELH_ERR_OOM;
   LevelData& L0 = H->lv[0];
@@ -1609,7 +1656,21 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
       return graphs_ok(H) ? run_graph(H, 0, adj, nrhs, v, z, fn) : fn();
     };
     rc = gmres<double, double>(H, H->kout[0], len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol,
-                               gs, nullptr);
+                               gs, nullptr, x0);
+  } else if (!opts->store_z_fp32) {
+    // float32 cycle, z_j widened to complex128: the cycle reads a float32
+    // copy of v_j and writes float32 into a level-0 work buffer, which is
+    // widened into Z (exact); everything else is the float64 solve
+    LevelData& W = H->lv[0];
+    auto M = [&](const void* v, void* z) {
+      CHK((launch_scale_copy<cx<double>, cx<float>>(nullptr, v, len, W.b[1].p, len, len, nrhs, H->st)));
+      auto fn = [&]() { return cycle<float>(H, 0, adj, W.b[1].p, W.x[1].p, nrhs); };
+      CHK(graphs_ok(H) ? run_graph(H, 1, adj, nrhs, W.b[1].p, W.x[1].p, fn) : fn());
+      return launch_scale_copy<cx<float>, cx<double>>(nullptr, W.x[1].p, len, z, len, len, nrhs, H->st);
+    };
+    auto AZ = [&](const void* zi, void* wo) { return op_apply<double>(H, 0, false, adj, zi, nullptr, wo, nrhs); };
+    rc = gmres<double, double>(H, H->kout[0], len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol,
+                               gs, nullptr, x0);
   } else {
     // float32 cycle (Section 5.3 mixed precision): the cycle reads a
     // float32 copy of the basis vector (written by the Gram-Schmidt pass)
@@ -1629,7 +1690,7 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
       return op_apply<double>(H, 0, false, adj, ws.t.p, nullptr, wo, nrhs);
     };
     rc = gmres<double, float>(H, ws, len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol, gs,
-                              L0.b[1].p);
+                              L0.b[1].p, x0);
   }
   if (rc < 0) return rc;
   const double wall =

@@ -24,6 +24,11 @@ int launch_restrict(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const
 template <typename T>
 int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* e, void* x, int nrhs,
                        hipStream_t st);
+// rc = R (b - H_s x) in one point-wise launch (one thread per coarse cell)
+template <typename T>
+int launch_restrict_resid(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, bool adj, const void* x,
+                          const void* b, void* rc, int nrhs, hipStream_t st);
+
 // 3D forward apply / residual, component-split wavefront march: three
 // wavefronts per x_2 row (one per displacement component) marching along
 // x_3, DPP for x_1 neighbours, one LDS hand-off per plane for the p row.
@@ -35,6 +40,14 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
 template <typename T>
 int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
                           hipStream_t st);
+// rc = R (b - H_s x) (adj: H_s^H) fused into the march: a workgroup of
+// seven wavefronts computes the residual rows of fine rows 2J and 2J+1 (and
+// the u_2 rows of row 2J-1) and restricts them to coarse row J; the fine
+// residual is never stored.  zc: x_3 chunk in coarse planes (< 0: exactly
+// -zc).  F must have even n (it has a coarser level).
+template <typename T>
+int launch_restrict_resid3d_w3(const LevelArgs<T>& F, const LevelArgs<T>& C, bool adj, const void* x,
+                               const void* b, void* rc, int nrhs, int zc, hipStream_t st);
 int launch_coarsen_media(int dim, const int* nf, const double* a, double* out, hipStream_t st);
 int launch_media_finish(int64_t n, const double* lam, const double* mu, const double* rho, double* kap, float* mu32,
                         float* rho32, float* kap32, hipStream_t st);

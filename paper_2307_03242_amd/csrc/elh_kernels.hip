@@ -445,6 +445,61 @@ __global__ void __launch_bounds__(256) k_restrict(LevelArgs<T> F, LevelArgs<T> C
   os[DIM * C.fs + cell] = (T(1) / T(nch)) * acc;
 }
 
+// Fused residual and restriction, one thread per coarse cell: rc = R (b -
+// H_s x) with every fine residual row the restriction needs evaluated in
+// place by the row evaluators (no fine residual is stored).  The face-normal
+// full weighting makes a fine face between two coarse faces count for both,
+// so about 1.4 row evaluations per fine row; this form serves the 2D and the
+// small 3D levels, where launches dominate.  Weights and their order as
+// k_restrict.
+template <int DIM, bool ADJ, typename T>
+__global__ void __launch_bounds__(256) k_restrict_resid(LevelArgs<T> F, LevelArgs<T> C, const cx<T>* __restrict__ x,
+                                                         const cx<T>* __restrict__ b, cx<T>* __restrict__ rc,
+                                                         int nrhs) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (cell >= C.fs || s >= nrhs) return;
+  int c[3];
+  c[0] = (int)(cell % C.n[0]);
+  c[1] = (int)((cell / C.n[0]) % C.n[1]);
+  c[2] = (int)(cell / ((int64_t)C.n[0] * C.n[1]));
+  const cx<T>* xs = x + s * F.vs;
+  const cx<T>* bs = b + s * F.vs;
+  cx<T>* os = rc + s * C.vs;
+  const T tw = DIM == 3 ? T(0.25) : T(0.5);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    cx<T> acc = czero<T>();
+    if (c[k] >= 1) {
+      for (int o = -1; o <= 1; ++o) {
+        const T wk = o == 0 ? T(0.5) : T(0.25);
+        const int nb = DIM == 3 ? 4 : 2;
+        for (int bb = 0; bb < nb; ++bb) {
+          int j[3] = {2 * c[0], 2 * c[1], DIM == 3 ? 2 * c[2] : 0};
+          int bit = 0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            if (a == k) continue;
+            j[a] += (bb >> bit) & 1;
+            ++bit;
+          }
+          j[k] = 2 * c[k] + o;  // >= 1: never a boundary face
+          const cx<T> r = bs[k * F.fs + lin<DIM>(F.n, j)] - eval_u<DIM, ADJ>(xs, F, k, j);
+          acc += (wk * tw) * r;
+        }
+      }
+    }
+    os[k * C.fs + cell] = acc;
+  }
+  cx<T> acc = czero<T>();
+  const int nch = DIM == 3 ? 8 : 4;
+  for (int bb = 0; bb < nch; ++bb) {
+    int j[3] = {2 * c[0] + (bb & 1), 2 * c[1] + ((bb >> 1) & 1), DIM == 3 ? 2 * c[2] + ((bb >> 2) & 1) : 0};
+    acc += bs[DIM * F.fs + lin<DIM>(F.n, j)] - eval_p<DIM, ADJ>(xs, F, j);
+  }
+  os[DIM * C.fs + cell] = (T(1) / T(nch)) * acc;
+}
+
 template <int DIM, typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(LevelArgs<T> F, LevelArgs<T> C, const cx<T>* __restrict__ e,
                                                       cx<T>* __restrict__ x, int nrhs) {
@@ -599,6 +654,28 @@ int launch_restrict(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const
     hipLaunchKernelGGL((k_restrict<2, T>), grd, blk, 0, st, F, C, (const cx<T>*)r, (cx<T>*)rc, nrhs);
   return (int)hipGetLastError();
 }
+template <typename T>
+int launch_restrict_resid(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, bool adj, const void* x,
+                          const void* b, void* rc, int nrhs, hipStream_t st) {
+  dim3 blk(C.fs < 256 * 64 ? 64 : 256);
+  dim3 grd((unsigned)((C.fs + blk.x - 1) / blk.x), nrhs);
+  const cx<T>* xp = (const cx<T>*)x;
+  const cx<T>* bp = (const cx<T>*)b;
+  cx<T>* op = (cx<T>*)rc;
+  if (dim == 3) {
+    if (adj) hipLaunchKernelGGL((k_restrict_resid<3, true, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
+    else hipLaunchKernelGGL((k_restrict_resid<3, false, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
+  } else {
+    if (adj) hipLaunchKernelGGL((k_restrict_resid<2, true, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
+    else hipLaunchKernelGGL((k_restrict_resid<2, false, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
+  }
+  return (int)hipGetLastError();
+}
+template int launch_restrict_resid<double>(const LevelArgs<double>&, const LevelArgs<double>&, int, bool,
+                                           const void*, const void*, void*, int, hipStream_t);
+template int launch_restrict_resid<float>(const LevelArgs<float>&, const LevelArgs<float>&, int, bool, const void*,
+                                          const void*, void*, int, hipStream_t);
+
 template <typename T>
 int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* e, void* x, int nrhs,
                        hipStream_t st) {

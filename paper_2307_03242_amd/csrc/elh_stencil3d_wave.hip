@@ -112,18 +112,52 @@ template <typename T> struct W3Ctx {
   T h, len1, len2, len3, abl_w, abl_iw, abl_amp, gam;
   const T* ablz;  // x_3 part of the absorbing layer per plane (centres, then lower faces)
   T gf;         // gamma (+alpha) + x_1 and x_2 parts of the layer at this wave's faces
+  // fused restriction of the residual (restriction mode only)
+  int role;     // 0: fine row 2J (stores coarse row J), 1: fine row 2J+1, 2: the u_2 rows of fine row 2J-1
+  int Jc, Z0, Z1, nc1, nc2;  // coarse row, coarse planes [Z0, Z1) of the chunk, coarse cells along x_1, x_2
+  int64_t cfs;               // coarse cells per field
+  cx<T>* yc;                 // coarse vector of this right-hand side
+  cx<T> (*RZ)[5][WV_LANES];  // LDS hand-off by coarse-plane parity: rows 2J+1 (u_1..u_3, p) and 2J-1 (u_2)
 };
+
+// Restriction along x_1 of a residual row held one fine face / cell per
+// lane: the full weighting (1/4)[1 2 1] for u_1 (FN == 0), the pair mean
+// otherwise; the result is meaningful at lanes holding an even c_1.
+template <int FN, typename T>
+__device__ __forceinline__ cx<T> rr_x1(cx<T> r) {
+  if (FN == 0) return T(0.25) * (fromL(r) + fromR(r)) + T(0.5) * r;
+  return T(0.5) * (r + fromR(r));
+}
+
+// x_2 step of the fused restriction and the store of coarse plane I3 of
+// coarse row J by the waves of fine row 2J: u_2 takes (1/4)[1 2 1] over
+// fine rows 2J-1, 2J, 2J+1, the other fields the pair mean of rows 2J and
+// 2J+1.  Coarse faces on the domain boundary are written as zero.
+template <int K, typename T>
+__device__ __forceinline__ void rr_emit(const W3Ctx<T>& C, int I3, cx<T> rz, cx<T> rzp) {
+  const int lane = threadIdx.x;
+  const int par = I3 & 1;
+  cx<T> v;
+  if (K == 1) v = T(0.5) * rz + T(0.25) * (C.RZ[par][1][lane] + C.RZ[par][4][lane]);
+  else v = T(0.5) * (rz + C.RZ[par][K][lane]);
+  if ((lane & 1) == 0 && lane >= 2 && lane <= WV_LANES - 4 && C.c1 < C.n1) {
+    const int I1 = C.c1 >> 1;
+    const bool bnd = K == 0 ? I1 == 0 : (K == 1 ? C.Jc == 0 : I3 == 0);
+    const int64_t o = ((int64_t)I3 * C.nc2 + C.Jc) * C.nc1 + I1;
+    C.yc[K * C.cfs + o] = bnd ? czero<T>() : v;
+    if (K == 0) C.yc[3 * C.cfs + o] = T(0.5) * (rzp + C.RZ[par][3][lane]);
+  }
+}
 
 // Per-wavefront context of the march: tile coordinates, clamped row
 // offsets, buffer resources, constants, gamma~ of this wavefront's faces.
 template <typename T, typename TI, bool RESID>
 __device__ __forceinline__ void w3_setup(W3Ctx<T>& C, const LevelArgs<T>& L, const cx<TI>* __restrict__ x,
-                                         const cx<T>* __restrict__ b, cx<T>* __restrict__ y, int tx, int c2, int tz,
-                                         int zc, int s) {
-  const int k = threadIdx.y;
+                                         const cx<T>* __restrict__ b, cx<T>* __restrict__ y, int c1o, int k, int c2,
+                                         int tz, int zc, int s) {
   C.n1 = L.n[0]; C.n2 = L.n[1]; C.n3 = L.n[2];
   C.plane = C.n1 * C.n2;
-  C.c1 = tx * WV_OUT - 1 + (int)threadIdx.x;
+  C.c1 = c1o + (int)threadIdx.x;
   C.c2 = c2;
   C.z0 = tz * zc;
   C.z1 = min(C.z0 + zc, C.n3);
@@ -136,7 +170,7 @@ __device__ __forceinline__ void w3_setup(W3Ctx<T>& C, const LevelArgs<T>& L, con
     C.rok[r] = rr >= 0 && rr < C.n2;
     C.roff[r] = min(max(rr, 0), C.n2 - 1) * C.n1 + cc1;
   }
-  C.offLc = c2 * C.n1 + max(cc1 - 1, 0);
+  C.offLc = min(max(c2, 0), C.n2 - 1) * C.n1 + max(cc1 - 1, 0);
   const int64_t fs = L.fs;
   const cx<TI>* xs = x + (int64_t)s * L.vs;
   cx<T>* ys = y + (int64_t)s * L.vs;
@@ -170,7 +204,11 @@ __device__ __forceinline__ void w3_setup(W3Ctx<T>& C, const LevelArgs<T>& L, con
   }
 }
 
-template <int K, typename T, typename TI, bool RESID>
+// RR (restriction mode, RESID true): the residual rows are restricted to
+// the coarse level instead of stored; the march then takes its planes in
+// (odd, even) pairs from 2 Z0 - 3, so that the residual of plane 2 Z0 - 1,
+// which the x_3 full weighting of u_3 needs, is exact.
+template <int K, typename T, typename TI, bool RESID, bool RR = false>
 __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
   constexpr int CB = (int)sizeof(cx<T>), CBI = (int)sizeof(cx<TI>), RBY = (int)sizeof(T);
   const T q = T(0.25), hf = T(0.5);
@@ -253,7 +291,11 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
   // the loop below takes planes in pairs, and anchoring the pairs to even
   // planes makes every plane go through the same copy of the step whatever
   // the chunk length, so all chunk lengths give the same bits
-  const int t0 = C.z0 - 2 - (C.z0 & 1);
+  const int t0 = RR ? C.z0 - 3 : C.z0 - 2 - (C.z0 & 1);
+  // restriction mode: x_1-restricted residual at planes t-1, t-2 (p row:
+  // rxp1), and the x_1/x_3-restricted values of the last odd plane kept by
+  // the waves of row 2J until the x_2 step
+  cx<T> rx1 = czero<T>(), rx2 = czero<T>(), rz = czero<T>(), rxp1 = czero<T>(), rzp = czero<T>();
 #pragma unroll
   for (int r = 0; r < 3; ++r) UA[r] = UB[r] = czero<T>();
   WA = WB = Y3b = F3 = Wmp = czero<T>();
@@ -268,8 +310,8 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
   }
   load_next(t0 + 1);
 
-  auto step = [&](int t, cx<T>(&UO)[3], cx<T>(&UC)[3], cx<T>& WO, cx<T>& WC, T(&MO)[3], T(&MC)[3], cx<T>& PO,
-                  cx<T>& PC) {
+  auto step = [&](int t, bool odd, cx<T>(&UO)[3], cx<T>(&UC)[3], cx<T>& WO, cx<T>& WC, T(&MO)[3], T(&MC)[3],
+                  cx<T>& PO, cx<T>& PC) {
     const int tn = t + 1;
     const bool zok = tn >= 0 && tn < n3;
     const int sc = zcl(t) * CB;
@@ -348,8 +390,19 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
     if (K == 0) acc += C.ih * (PC - fromL(PC));
     if (K == 1) acc += C.ih * (PC - Pbm);
     if (K == 2) acc += C.ih * (PC - PO);
-    const bool emit = C.outlane && t >= C.z0;
-    if (emit) {
+    const bool emit = !RR && C.outlane && t >= C.z0;
+    if (RR) {
+      // every lane takes part in the lane shifts; boundary faces feed only
+      // coarse boundary faces, which are written as zero
+      const cx<T> rx = rr_x1<K>(bq - acc);
+      if (odd) {
+        const cx<T> v = K == 2 ? q * (rx2 + rx) + hf * rx1 : hf * (rx1 + rx);
+        if (C.role != 0) C.RZ[(t >> 1) & 1][C.role == 1 ? K : 4][lane] = v;
+        rz = v;  // used by row 2J only
+      }
+      rx2 = rx1;
+      rx1 = rx;
+    } else if (emit) {
       const bool face = K == 0 ? C.c1 > 0 : (K == 1 ? C.c2 > 0 : t > 0);
       cx<T> v = face ? acc : czero<T>();
       if (RESID && face) v = bq - v;
@@ -371,18 +424,35 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
     PO = Pnc;
     Pbm = Pnm;
     lds_barrier_w3();
-    if (K == 0 && emit) {
+    if (K == 0 && (emit || (RR && C.role != 2))) {
       cx<T> vp = C.ih * dv + DV[t & 1][1][lane] + DV[t & 1][2][lane];
       const T kq = PF ? kqp : bload<T>(C.RKAP, vr[2], zcl(t) * RBY);
       vp += kq * PC;
       if (RESID) vp = (PF ? bpp : bload<cx<T>>(C.RB[3], vu[1], sc)) - vp;
-      bstore(vp, C.RY[3], vu[1], sc);
+      if (RR) {
+        const cx<T> rxp = rr_x1<3>(vp);
+        if (odd) {
+          const cx<T> v = hf * (rxp1 + rxp);
+          if (C.role != 0) C.RZ[(t >> 1) & 1][3][lane] = v;
+          rzp = v;
+        }
+        rxp1 = rxp;
+      } else {
+        bstore(vp, C.RY[3], vu[1], sc);
+      }
     }
+    // coarse plane (t - 2) / 2, handed over before this plane's barrier
+    if (RR && !odd && C.role == 0 && t >= 2 * C.Z0 + 2) rr_emit<K>(C, (t >> 1) - 1, rz, rzp);
   };
 
   for (int t = t0; t < C.z1; t += 2) {
-    step(t, UA, UB, WA, WB, MA, MB, PA, PB);
-    if (t + 1 < C.z1) step(t + 1, UB, UA, WB, WA, MB, MA, PB, PA);
+    step(t, RR, UA, UB, WA, WB, MA, MB, PA, PB);
+    if (t + 1 < C.z1) step(t + 1, !RR, UB, UA, WB, WA, MB, MA, PB, PA);
+  }
+  if (RR) {
+    // the last odd plane of the chunk: its coarse plane Z1 - 1
+    lds_barrier_w3();
+    if (C.role == 0) rr_emit<K>(C, C.Z1 - 1, rz, rzp);
   }
 }
 
@@ -396,7 +466,9 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
 // and t+1 (rows c-1..c+1); A_2 G_1 at planes t-1, t; A_1 G_2 at the two
 // flux rows, planes t-1, t; the spread x_3 flux below plane t; the
 // attenuated u of the mass at (c, t-1), (c, t); the partial spreads of p.
-template <int K, typename T, bool RESID>
+// RR: restriction mode as in w3_march (one step per plane here, so the
+// plane parity is a run-time value).
+template <int K, typename T, bool RESID, bool RR = false>
 __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
   constexpr int CB = (int)sizeof(cx<T>), RBY = (int)sizeof(T);
   const T q = T(0.25), hf = T(0.5);
@@ -492,7 +564,8 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
   T mubL[3];                   // K == 0: mu one cell to the left at plane t (rows c-1..c+1)
   T rhoa, rhob0, rhob1;        // rho: (c, t-1); plane t rows (K == 1: c-1, c; else c)
   T a3a, a3b;                  // x_3 part of gamma~ at planes t-1, t
-  const int t0 = C.z0 - 2;
+  const int t0 = RR ? C.z0 - 3 : C.z0 - 2;
+  cx<T> rx1 = czero<T>(), rx2 = czero<T>(), rz = czero<T>(), rxp1 = czero<T>(), rzp = czero<T>();
 #pragma unroll
   for (int r = 0; r < 3; ++r) UC[r] = czero<T>();
   X1a = X1b = G1b = Q2la = Q2lb = Q2ha = Q2hb = G2lb = G2hb = SG3 = Wa = Wb = czero<T>();
@@ -620,8 +693,18 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
       dv = UC[1] - Un[1];
       Pa0 = Pb0; Pb0 = SPn;
     }
-    const bool emit = C.outlane && t >= C.z0;
-    if (emit) {
+    const bool emit = !RR && C.outlane && t >= C.z0;
+    const bool odd = t & 1;
+    if (RR) {
+      const cx<T> rx = rr_x1<K>(bq - acc);
+      if (odd) {
+        const cx<T> v = K == 2 ? q * (rx2 + rx) + hf * rx1 : hf * (rx1 + rx);
+        if (C.role != 0) C.RZ[(t >> 1) & 1][C.role == 1 ? K : 4][lane] = v;
+        rz = v;  // used by row 2J only
+      }
+      rx2 = rx1;
+      rx1 = rx;
+    } else if (emit) {
       const bool face = K == 0 ? C.c1 > 0 : (K == 1 ? C.c2 > 0 : t > 0);
       cx<T> v = face ? acc : czero<T>();
       if (RESID && face) v = bq - v;
@@ -642,13 +725,28 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
     rhoa = rhob1; rhob0 = rhon0; rhob1 = rhon1;
     a3a = a3b; a3b = a3n;
     lds_barrier_w3();
-    if (K == 0 && emit) {
+    if (K == 0 && (emit || (RR && C.role != 2))) {
       // p row of cell (c1, c2, t): kappa p + the three differences
       cx<T> vp = DV[t & 1][0][lane] + DV[t & 1][1][lane] + DV[t & 1][2][lane];
       vp += kq * Pc1;
       if (RESID) vp = bp - vp;
-      bstore(vp, C.RY[3], vu[1], sc);
+      if (RR) {
+        const cx<T> rxp = rr_x1<3>(vp);
+        if (odd) {
+          const cx<T> v = hf * (rxp1 + rxp);
+          if (C.role != 0) C.RZ[(t >> 1) & 1][3][lane] = v;
+          rzp = v;
+        }
+        rxp1 = rxp;
+      } else {
+        bstore(vp, C.RY[3], vu[1], sc);
+      }
     }
+    if (RR && !odd && C.role == 0 && t >= 2 * C.Z0 + 2) rr_emit<K>(C, (t >> 1) - 1, rz, rzp);
+  }
+  if (RR) {
+    lds_barrier_w3();
+    if (C.role == 0) rr_emit<K>(C, C.Z1 - 1, rz, rzp);
   }
   (void)a3a;
 }
@@ -667,8 +765,8 @@ k_apply3d_w3_adj(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __res
   const int tz = rest % nzc; rest /= nzc;
   const int s = rest;
   W3Ctx<T> C;
-  w3_setup<T, T, RESID>(C, L, x, b, y, tx, c2, tz, zc, s);
   const int k = threadIdx.y;
+  w3_setup<T, T, RESID>(C, L, x, b, y, tx * WV_OUT - 1, k, c2, tz, zc, s);
   if (k == 0) w3_march_adj<0, T, RESID>(C, DV);
   else if (k == 1) w3_march_adj<1, T, RESID>(C, DV);
   else w3_march_adj<2, T, RESID>(C, DV);
@@ -688,11 +786,65 @@ k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restri
   const int tz = rest % nzc; rest /= nzc;
   const int s = rest;
   W3Ctx<T> C;
-  w3_setup<T, TI, RESID>(C, L, x, b, y, tx, c2, tz, zc, s);
   const int k = threadIdx.y;
+  w3_setup<T, TI, RESID>(C, L, x, b, y, tx * WV_OUT - 1, k, c2, tz, zc, s);
   if (k == 0) w3_march<0, T, TI, RESID>(C, DV);
   else if (k == 1) w3_march<1, T, TI, RESID>(C, DV);
   else w3_march<2, T, TI, RESID>(C, DV);
+}
+
+// Residual + restriction, rc = R (b - H_s x) (ADJ: H_s^H): a workgroup of
+// seven wavefronts for coarse row J of a 60-wide x_1 segment (fine cells
+// c_1 = 60 tx - 2 + lane; lanes 1 and 62 are exact residual rows used by the
+// full weighting, 0 and 63 halo) and a chunk of coarse planes.  Waves 0-2
+// march fine row 2J (components u_1..u_3; wave 0 also the p row), waves 3-5
+// row 2J+1, wave 6 the u_2 rows of row 2J-1.  Each restricts its residual
+// along x_1 (lane shifts) and x_3 (register window); rows 2J+1 and 2J-1 hand
+// theirs to row 2J through LDS, which does the x_2 step and the store.
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(WV_LANES * 7)
+k_restrict_resid3d_w3(LevelArgs<T> L, LevelArgs<T> Lc, const cx<T>* __restrict__ x, const cx<T>* __restrict__ b,
+                      cx<T>* __restrict__ yc, int tiles_x, int nzc, int zc, int ntiles, int per_xcd) {
+  __shared__ cx<T> DV[3][2][3][WV_LANES];  // per fine row (2J, 2J+1; unused third for wave 6)
+  __shared__ cx<T> RZ[2][5][WV_LANES];
+  const int bid = blockIdx.x;
+  const int tile = (bid & 7) * per_xcd + (bid >> 3);
+  if (tile >= ntiles) return;  // whole workgroup
+  int rest = tile;
+  const int tx = rest % tiles_x; rest /= tiles_x;
+  const int J = rest % Lc.n[1]; rest /= Lc.n[1];
+  const int tz = rest % nzc; rest /= nzc;
+  const int s = rest;
+  // the wave's index, as a wave-uniform (scalar) value: the role branches
+  // below are then scalar branches
+  const int wy = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+  const int role = wy < 3 ? 0 : (wy < 6 ? 1 : 2);
+  const int k = wy < 6 ? wy % 3 : 1;
+  const int c2 = 2 * J + (role == 1 ? 1 : (role == 2 ? -1 : 0));
+  W3Ctx<T> C;
+  // (the fine-level y resources are never stored through in this mode)
+  w3_setup<T, T, true>(C, L, x, b, const_cast<cx<T>*>(b), tx * (WV_OUT - 2) - 2, k, c2, 0, 1, s);
+  C.role = role;
+  C.Jc = J;
+  C.nc1 = Lc.n[0];
+  C.nc2 = Lc.n[1];
+  C.cfs = Lc.fs;
+  C.yc = yc + (int64_t)s * Lc.vs;
+  C.RZ = RZ;
+  C.Z0 = tz * zc;
+  C.Z1 = min(C.Z0 + zc, Lc.n[2]);
+  C.z0 = 2 * C.Z0;
+  C.z1 = 2 * C.Z1;
+  cx<T>(*dv)[3][WV_LANES] = DV[role];
+  if (ADJ) {
+    if (k == 0) w3_march_adj<0, T, true, true>(C, dv);
+    else if (k == 1) w3_march_adj<1, T, true, true>(C, dv);
+    else w3_march_adj<2, T, true, true>(C, dv);
+  } else {
+    if (k == 0) w3_march<0, T, T, true, true>(C, dv);
+    else if (k == 1) w3_march<1, T, T, true, true>(C, dv);
+    else w3_march<2, T, T, true, true>(C, dv);
+  }
 }
 
 // x_3 chunk length: zc < 0 asks for exactly -zc planes (the autotuner's
@@ -749,6 +901,36 @@ int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, v
                        (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
   return (int)hipGetLastError();
 }
+template <typename T>
+int launch_restrict_resid3d_w3(const LevelArgs<T>& F, const LevelArgs<T>& Cl, bool adj, const void* x,
+                               const void* b, void* rc, int nrhs, int zc, hipStream_t st) {
+  if (F.fs * (int64_t)sizeof(cx<T>) > (int64_t)0x7fffffff) return (int)hipErrorInvalidValue;
+  if (!x || !b || (F.n[0] & 1) || (F.n[1] & 1) || (F.n[2] & 1) || Cl.n[0] * 2 != F.n[0] ||
+      Cl.n[1] * 2 != F.n[1] || Cl.n[2] * 2 != F.n[2])
+    return (int)hipErrorInvalidValue;
+  const int tiles_x = (F.n[0] + (WV_OUT - 2) - 1) / (WV_OUT - 2);
+  // chunk in coarse planes (same heuristic, counted on the coarse rows)
+  const int nc[3] = {Cl.n[0], Cl.n[1], Cl.n[2]};
+  zc = w3_chunk(nc, tiles_x, nrhs, zc);
+  const int nzc = (Cl.n[2] + zc - 1) / zc;
+  const int64_t ntiles64 = (int64_t)tiles_x * Cl.n[1] * nzc * nrhs;
+  if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
+  const int ntiles = (int)ntiles64;
+  const int per_xcd = (ntiles + 7) / 8;
+  dim3 blk(WV_LANES, 7), grd(8 * per_xcd);
+  if (adj)
+    hipLaunchKernelGGL((k_restrict_resid3d_w3<T, true>), grd, blk, 0, st, F, Cl, (const cx<T>*)x, (const cx<T>*)b,
+                       (cx<T>*)rc, tiles_x, nzc, zc, ntiles, per_xcd);
+  else
+    hipLaunchKernelGGL((k_restrict_resid3d_w3<T, false>), grd, blk, 0, st, F, Cl, (const cx<T>*)x,
+                       (const cx<T>*)b, (cx<T>*)rc, tiles_x, nzc, zc, ntiles, per_xcd);
+  return (int)hipGetLastError();
+}
+template int launch_restrict_resid3d_w3<double>(const LevelArgs<double>&, const LevelArgs<double>&, bool,
+                                                const void*, const void*, void*, int, int, hipStream_t);
+template int launch_restrict_resid3d_w3<float>(const LevelArgs<float>&, const LevelArgs<float>&, bool, const void*,
+                                               const void*, void*, int, int, hipStream_t);
+
 template int launch_apply3d_w3_adj<double>(const LevelArgs<double>&, const void*, const void*, void*, int, int,
                                            hipStream_t);
 template int launch_apply3d_w3_adj<float>(const LevelArgs<float>&, const void*, const void*, void*, int, int,

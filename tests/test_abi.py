@@ -126,3 +126,26 @@ def test_solve_and_gradient_check_their_buffers_without_gpu():
     for bad in (q.to(torch.complex64), q[:1].clone(), torch.zeros((2, 4, 4, 4, 8), dtype=q.dtype)[..., :4]):
         with pytest.raises(ValueError):
             p.gradient(q, bad)
+
+
+def test_create_rejects_a_singular_shift_without_gpu():
+    """gamma + alpha must be positive (the shifted operator is then
+    nonsingular), neither negative, and omega positive: ELH_ERR_ARG before
+    any device call"""
+    from paper_2307_03242_amd import _lib
+    lib = _lib.load()
+    d = _lib.Desc()
+    d.dim = 3
+    d.n[0] = d.n[1] = d.n[2] = 8
+    d.h, d.beta, d.levels, d.omega = 1.0, 2 / 3, 2, 0.5
+    d.nu1 = d.nu2 = 1
+    d.cycle_calls = 1
+    d.coarse_sweeps, d.coarse_restart, d.coarse_maxit = 2, 5, 10
+    d.precond_dtype = _lib.ELH_C128
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)
+    for g, a, om in ((0.0, 0.0, 0.5), (-0.01, 0.3, 0.5), (0.01, -0.3, 0.5), (0.01, 0.3, 0.0),
+                     (float("nan"), 0.3, 0.5), (0.01, 0.3, float("inf"))):
+        d.gamma, d.alpha, d.omega = g, a, om
+        assert lib.elh_create(ctypes.byref(d), dummy, dummy, dummy, None, ctypes.byref(h)) == _lib.ELH_ERR_ARG
+        assert not h.value

@@ -130,3 +130,48 @@ def test_outer_operator_on_float32_input(shape, adjoint):
     ref = np.stack([O.apply(lv, x[s].astype(np.complex128), adjoint=adjoint) for s in range(2)])
     y = _host(prob.apply_f32_input(_dev(x, torch.complex64), adjoint=adjoint))
     assert _maxrel(y, ref) <= TOL64
+
+
+# n_1 = 70, 130 and 62: two, three and two x_1 segments of the 60-lane
+# restriction tiles with ragged last ones (62 puts two fine cells in the
+# last); n_3 = 10, 18 and 14 give 5, 9 and 7 coarse planes: ragged chunks
+RR_SHAPES = [(10, 12, 70), (18, 10, 130), (14, 16, 62)]
+
+
+@pytest.mark.parametrize("shape", RR_SHAPES)
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_marching_restrict_residual(shape, adjoint):
+    """R (b - H_s x) in one launch (fine residual never stored) against the
+    oracle's restriction of its residual, float64 and float32, two
+    right-hand sides"""
+    prob, lv = _setup(shape, levels=2)
+    lvc = C.coarsen_level(lv)
+    x = random_field(shape, 71, nrhs=2)
+    b = random_field(shape, 72, nrhs=2)
+    ref = np.stack([T.restrict(lv, b[s] - O.apply(lv, x[s], shift=0.3, adjoint=adjoint), lvc) for s in range(2)])
+    rc = _host(prob.restrict_residual(_dev(b), _dev(x), adjoint=adjoint))
+    assert _maxrel(rc, ref) <= TOL64
+    x32 = x.astype(np.complex64).astype(np.complex128)
+    b32 = b.astype(np.complex64).astype(np.complex128)
+    ref32 = np.stack([T.restrict(lv, b32[s] - O.apply(lv, x32[s], shift=0.3, adjoint=adjoint), lvc)
+                      for s in range(2)])
+    rc32 = _host(prob.restrict_residual(_dev(b, torch.complex64), _dev(x, torch.complex64), adjoint=adjoint))
+    assert _maxrel(rc32, ref32) <= TOL32
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_marching_restrict_residual_chunks_bitwise(adjoint, monkeypatch):
+    """every forced x_3 chunk (in coarse planes) gives bitwise the output of
+    the default chunk: the chunk only decides which workgroup marches which
+    planes"""
+    shape = (18, 10, 130)
+    x = _dev(random_field(shape, 73, nrhs=2), torch.complex64)
+    b = _dev(random_field(shape, 74, nrhs=2), torch.complex64)
+    monkeypatch.setenv("ELH_TUNE", "0")
+    prob, _ = _setup(shape, levels=2)
+    ref = prob.restrict_residual(b, x, adjoint=adjoint)
+    for c in (1, 2, 3, 4, 9):
+        monkeypatch.setenv("ELH_ZCHUNK", str(-c))
+        p2, _ = _setup(shape, levels=2)
+        got = p2.restrict_residual(b, x, adjoint=adjoint)
+        assert torch.equal(got, ref), c
