@@ -204,6 +204,24 @@ int elh_prolong_add(elh_handle* h, int level, int dtype, int nrhs,
 int elh_relax(elh_handle* h, int level, int flags, int dtype, int nrhs,
               int colour, const void* b, void* x);
 
+/* Allocation-free form of elh_relax, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same operation, arguments, results and
+ * errors as elh_relax, bitwise.  The residual work lives in one static
+ * device array per GPU of ELH_NOALLOC_SCRATCH_BYTES (64 MiB), which the
+ * library holds from its first elh_create on that GPU until the process
+ * ends; nrhs * (dim+1) * (cells of the level) * (8 for ELH_C64, 16 for
+ * ELH_C128) bytes must fit, else ELH_ERR_ARG before anything is launched
+ * (e.g. one complex64 right-hand side on up to 128^3 cells).  Calls no
+ * allocator and never runs the stencil autotuner (it uses a chunk the tuner
+ * chose earlier, else the default; the results are the same).  Every call on
+ * one GPU shares that array: calls that overlap in time on one GPU (other
+ * streams, other threads, other handles) race and give wrong results; calls
+ * ordered on one stream are safe. */
+#define ELH_NOALLOC_SCRATCH_BYTES (64u << 20)
+int elh_relax_noalloc(elh_handle* h, int level, int flags, int dtype, int nrhs,
+                      int colour, const void* b, void* x);
+
 /* x = coarsest-level solve of H_s x = b (mode desc->coarse_mode) on level
  * levels-1. */
 int elh_coarse_solve(elh_handle* h, int flags, int dtype, int nrhs,

@@ -13,7 +13,7 @@ ELH_COARSE_KRYLOV, ELH_COARSE_DENSE, ELH_COARSE_RELAX, ELH_COARSE_KACZMARZ = 0, 
 
 EXPORTED = [
     "elh_create", "elh_set_media", "elh_destroy", "elh_apply", "elh_residual",
-    "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_coarse_solve", "elh_kaczmarz", "elh_apply_f32in",
+    "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_relax_noalloc", "elh_coarse_solve", "elh_kaczmarz", "elh_apply_f32in",
     "elh_vcycle", "elh_solve", "elh_solve_adjoint", "elh_solve_batch", "elh_gradient",
     "elh_level_info", "elh_stencil_choice", "elh_status_string", "elh_last_error",
 ]
@@ -72,6 +72,7 @@ def load():
         "elh_restrict_residual": [H, ip, ip, ip, ip, vp, vp, vp],
         "elh_prolong_add": [H, ip, ip, ip, vp, vp],
         "elh_relax": [H, ip, ip, ip, ip, ip, vp, vp],
+        "elh_relax_noalloc": [H, ip, ip, ip, ip, ip, vp, vp],
         "elh_coarse_solve": [H, ip, ip, ip, vp, vp],
         "elh_kaczmarz": [H, ip, ip, ip, ip, vp, vp],
         "elh_apply_f32in": [H, ip, ip, vp, vp],

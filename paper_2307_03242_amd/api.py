@@ -209,6 +209,15 @@ class Problem:
                                    colour, _ptr(b), _ptr(x)))
         return x
 
+    def relax_noalloc(self, b, x, colour, level=0, adjoint=False):
+        """relax() through the allocation-free entry point (residual work in
+        the library's static per-GPU array; for callers that cannot allocate)"""
+        nrhs = self._vec(x, level)
+        self._same(b, x, "b")
+        L.check(self.lib.elh_relax_noalloc(self.handle, level, self._flags(False, adjoint), _dtype_code(x), nrhs,
+                                           colour, _ptr(b), _ptr(x)))
+        return x
+
     def coarse_solve(self, b, adjoint=False):
         nrhs = self._vec(b, self.levels - 1)
         x = torch.empty_like(b)

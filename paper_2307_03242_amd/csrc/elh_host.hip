@@ -138,6 +138,7 @@ struct elh_handle {
   std::map<int, int> tuned;
   hipEvent_t tev[2] = {nullptr, nullptr};
   std::string tune_path;
+  void* scratch = nullptr;  // this device's address of the allocation-free relaxation's work array
   int ok = 0;
 };
 
@@ -249,6 +250,32 @@ static int build_kaczmarz(elh_handle* H);
 static void tune_load(elh_handle* H);
 static int tune_key(int l, int prec, int iprec, int kind, bool adj, int nrhs);
 
+// Work array of the allocation-free relaxation (elh_relax_noalloc): a
+// file-scope device array, so the loaded code object gives every GPU its own
+// copy, held until the process ends.  Host code never uses the array's name
+// as an address: each device's address comes from hipGetSymbolAddress, once
+// per device, at elh_create (with that device current), and is kept here.
+static __device__ __align__(256) unsigned char scratch[ELH_NOALLOC_SCRATCH_BYTES];
+static constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+static int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return fail(ELH_ERR_HIP, "no usable current device for the relaxation work array");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ELH_ERR_HIP, "hipGetSymbolAddress of the relaxation work array failed: %s", hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return 0;
+}
+
 extern "C" int elh_create(const elh_desc* desc, const double* lam, const double* mu, const double* rho,
                           void* stream, elh_handle** out) {
   if (!out) return fail(ELH_ERR_ARG, "out is NULL");
@@ -332,7 +359,8 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
     elh_destroy(H);
     return fail(ELH_ERR_OOM, "pinned host allocation failed");
   }
-  rc = build_hierarchy(H, lam, mu, rho);
+  rc = scratch_address(&H->scratch);
+  if (!rc) rc = build_hierarchy(H, lam, mu, rho);
   if (!rc && desc->coarse_mode == ELH_COARSE_DENSE) rc = build_dense(H);
   if (!rc && desc->coarse_mode == ELH_COARSE_KACZMARZ) rc = build_kaczmarz(H);
   if (rc) {
@@ -622,6 +650,15 @@ static int op_relax(elh_handle* H, int l, bool adj, int colour, const void* b, v
   }
   return launch_vanka<T>(largs<T>(H, l, true), H->d.dim, adj, r, x, colour, level_damping(H, l), nrhs, H->st,
                          x_is_zero && H->d.dim == 3);
+}
+
+// one colour of red-black Vanka with the residual in the caller's work
+// buffer r; the stencil chunk is the autotuner's earlier choice or the
+// default (no tuning: nothing is timed or allocated)
+template <typename T>
+static int op_relax_with(elh_handle* H, int l, bool adj, int colour, const void* b, void* x, void* r, int nrhs) {
+  CHK(op_apply<T>(H, l, true, adj, x, b, r, nrhs, false));
+  return launch_vanka<T>(largs<T>(H, l, true), H->d.dim, adj, r, x, colour, level_damping(H, l), nrhs, H->st, false);
 }
 
 template <typename T>
@@ -1569,6 +1606,23 @@ extern "C" int elh_relax(elh_handle* H, int level, int flags, int dtype, int nrh
   bool adj = flags & ELH_ADJOINT;
   if (dtype == ELH_C128) CHK(op_relax<double>(H, level, adj, colour, b, x, nrhs, false));
   else CHK(op_relax<float>(H, level, adj, colour, b, x, nrhs, false));
+  return 0;
+}
+
+extern "C" int elh_relax_noalloc(elh_handle* H, int level, int flags, int dtype, int nrhs, int colour,
+                                 const void* b, void* x) {
+  int rc = check_common(H, level, dtype, nrhs);
+  if (rc) return rc;
+  if (colour != 0 && colour != 1) return fail(ELH_ERR_ARG, "colour must be 0 or 1");
+  if (!b || !x || b == x) return fail(ELH_ERR_ARG, "b and x must be distinct non-NULL pointers");
+  const size_t need = (size_t)nrhs * (size_t)H->lv[level].vs * csz(prec_of(dtype));
+  if (need > (size_t)ELH_NOALLOC_SCRATCH_BYTES)
+    return fail(ELH_ERR_ARG, "the residual of %d right-hand side(s) on level %d needs %zu bytes; the allocation-free "
+                "relaxation holds at most %zu", nrhs, level, need, (size_t)ELH_NOALLOC_SCRATCH_BYTES);
+  if (!H->scratch) return fail(ELH_ERR_STATE, "the relaxation work array has no device address");
+  const bool adj = flags & ELH_ADJOINT;
+  if (dtype == ELH_C128) CHK(op_relax_with<double>(H, level, adj, colour, b, x, H->scratch, nrhs));
+  else CHK(op_relax_with<float>(H, level, adj, colour, b, x, H->scratch, nrhs));
   return 0;
 }
 
