@@ -61,8 +61,10 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=64, help="oracle sample grid (cells per axis)")
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--pmc-target", action="store_true",
-                    help="run only a plain 1 GiB device copy (counter calibration) and the float32 residual at "
-                         "--n^3, three launches each, for rocprofv3 --pmc passes")
+                    help="run only a plain 1 GiB device copy (counter calibration) and, at --n^3 in complex64, the "
+                         "residual, the apply, a Vanka half-sweep (residual + block solves) and the fused residual "
+                         "restriction, each after one untimed call (which lets the autotuner choose) and then three "
+                         "times, for rocprofv3 --pmc passes")
     ap.add_argument("--paper-tables", action="store_true",
                     help="only the 2D iteration-count experiments of the paper's homogeneous and linear-media "
                          "tables (W(1,1) cycles, 2-4 levels, beta 1 and 2/3), counts beside the printed ones")
@@ -426,8 +428,15 @@ def main():
         xx = torch.from_numpy(random_field(shape, 1)).cuda().to(torch.complex64)
         bb = torch.from_numpy(random_field(shape, 2)).cuda().to(torch.complex64)
         rr = torch.empty_like(xx)
-        for _ in range(3):
+        yy = torch.empty_like(xx)
+        for _ in range(4):
             pr.residual(bb, xx, shifted=True, out=rr)
+        for _ in range(4):
+            pr.apply(xx, out=yy)
+        for _ in range(4):
+            pr.relax(bb, yy, 1)
+        for _ in range(4):
+            pr.restrict_residual(bb, xx)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_target": True, "copy_bytes_each_way": 1 << 30, "n": n,
                           "resid_algorithmic_bytes": RESID_BYTES_F32 * n ** 3}), flush=True)

@@ -294,20 +294,22 @@ int elh_gradient(elh_handle* h, int nrhs, const void* u, const void* v,
 int elh_level_info(elh_handle* h, int level, int* n3, double* hl);
 
 /* Stencil autotuner (batching / set-up row of the hot path).  On its first
- * use outside graph capture, each kind of 3D apply or residual (level,
- * precision, residual or not, adjoint or not, nrhs) times its candidate
- * x_3 chunks of the wavefront march (4, 8, 16, 32, 64 planes per workgroup;
- * on columns of at most 64 planes also 1, 2 and the whole column) on the call's own
- * buffers with HIP events on the handle's stream and keeps the fastest for
- * the handle's lifetime.  The chunk never changes an output's arithmetic,
- * so tuned and untuned results are bitwise equal.
+ * use outside graph capture, each kind of 3D march (level, precision, input
+ * precision, kind: 0 apply, 1 residual, 2 residual restricted to the next
+ * level; adjoint or not; nrhs) times its candidate x_3 chunks of the
+ * wavefront march (4, 8, 16, 32, 64 planes per workgroup; on columns of at
+ * most 64 planes also 1, 2 and the whole column; coarse planes for kind 2)
+ * on the call's own buffers with HIP events on the handle's stream and keeps
+ * the fastest for the handle's lifetime.  The chunk never changes an
+ * output's arithmetic, so tuned and untuned results are bitwise equal.
  * Environment: ELH_TUNE=0 (read at elh_create) keeps the default chunk
  * heuristic; ELH_TUNE_CACHE=path loads earlier choices for the handle's
  * grids at elh_create and appends new ones (one text line each).
  * elh_stencil_choice reports the choice for one kind of call: *choice (host)
- * = the chunk (> 0), or -1 when none has been made.  flags: ELH_ADJOINT selects the adjoint; residual: 0 or 1.
- * Returns ELH_ERR_STATE / ELH_ERR_ARG on an invalid handle, level, dtype or
- * NULL choice. */
+ * = the chunk (> 0), or -1 when none has been made.  flags: ELH_ADJOINT
+ * selects the adjoint; residual: the kind (0, 1, 2).
+ * Returns ELH_ERR_STATE / ELH_ERR_ARG on an invalid handle, level, dtype,
+ * kind or NULL choice. */
 int elh_stencil_choice(elh_handle* h, int level, int dtype, int flags,
                        int residual, int nrhs, int* choice);
 
