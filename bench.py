@@ -31,11 +31,20 @@ APPLY_BYTES_F64 = 152      # algorithmic bytes per cell of one operator apply (x
 APPLY_BYTES_F32 = 76
 RESID_BYTES_F32 = 108      # residual b - H_s x in complex64: x, b, y (32 B each) + mu, rho, kappa (float32)
 # HBM bytes per launch of the float32 residual at 256^3 from the rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes over `bench.py --pmc-target` (each scaled
-# by what the same counter reads for a 1 GiB device copy: x2.0 for FETCH_SIZE,
-# x1.0 for WRITE_SIZE): 1.484 GB read + 0.559 GB written.  Set to None when
-# the kernel changes until the passes are repeated.
-RESID_TRAFFIC_BYTES = 2.113e9
+# FETCH_SIZE / WRITE_SIZE passes over `bench.py --pmc-target`
+# (profiles/stencil_256cubed_counters.md; FETCH_SIZE x2.0, WRITE_SIZE x1.0):
+# 1.596 GB read + 0.556 GB written, measured on the kernel source whose
+# SHA-256 prefix is RESID_TRAFFIC_SOURCE.  When the source changes the
+# figure is not reported (null) until the passes are repeated.
+RESID_TRAFFIC_BYTES = 2.152e9
+RESID_TRAFFIC_SOURCE = "4c166550fecd58a5"
+STENCIL_SOURCE = os.path.join(ROOT, "paper_2307_03242_amd", "csrc", "elh_stencil3d_wave.hip")
+
+
+def stencil_source_hash():
+    import hashlib
+    with open(STENCIL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def parse():
@@ -85,7 +94,7 @@ def cpu_baseline(args, gpu_iters, cfg):
     from threadpoolctl import threadpool_limits
     from oracle import grid as G, operator as O, cycle as C
     from oracle.krylov import fgmres
-    from synthetic import make_media, point_source, omega_for_ppw
+    from synthetic import make_media, point_source, omega_for_ppw, random_field
     n = args.cpu_n
     shape = (n, n, n)
     m = make_media(shape, args.seed)
@@ -106,10 +115,36 @@ def cpu_baseline(args, gpu_iters, cfg):
         dt = time.perf_counter() - t0
     per_iter_cell = dt / info["iters"] / (n ** 3)
     t_solve = per_iter_cell * (args.n ** 3) * gpu_iters
+    # the oracle's matrix-free apply, measured at full sizes (one core)
+    applies = {}
+    for na in (128, args.n):
+        if na in applies or na <= 0:
+            continue
+        ma = make_media((na, na, na), args.seed)
+        la = G.Level((na, na, na), 1.0, omega_for_ppw(ma["vs"].min(), 1.0, 10), 0.01, 2 / 3, ma["lam"], ma["mu"],
+                     ma["rho"], abl_width=args.abl * 1.0, abl_amp=2.0)
+        xa = random_field((na, na, na), 1)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            ya = O.apply(la, xa)
+            ta = time.perf_counter() - t0
+        applies["%d^3" % na] = {"seconds": ta, "GBps": APPLY_BYTES_F64 * na ** 3 / ta / 1e9}
+        del ma, la, xa, ya
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": "%d outer FGMRES(5)+%s-cycle iterations of the float64 oracle on a %d^3 grid "
                       "(same media recipe, %.1f s), scaled per cell to %d^3 and to the GPU's %d iterations"
-                      % (info["iters"], args.cycle, n, dt, args.n, gpu_iters)}
+                      % (info["iters"], args.cycle, n, dt, args.n, gpu_iters),
+            "cpu_model": cpu_model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "oracle_apply_measured": applies}
 
 
 def solver_cfg(args, omega, levels=None):
@@ -147,59 +182,67 @@ def extras(args):
     _, info, code = p32.solve(q, rtol=args.rtol, maxit=args.maxit)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    iters32 = [i["iters"] for i in info]
     del p32
     torch.cuda.empty_cache()
-    old = os.environ.get("ELH_GRAPHS")
-    os.environ["ELH_GRAPHS"] = "0"
-    try:
-        p64 = Problem(*med, precond_dtype=torch.complex128, **solver_cfg(args, om))
-    finally:
-        if old is None:
-            del os.environ["ELH_GRAPHS"]
-        else:
-            os.environ["ELH_GRAPHS"] = old
-    nsingle = 4
+    # the plain float64 solver with the library's defaults (graphs on), one
+    # source per solve, all 32 sources (after one untimed solve that tunes);
+    # and the same float64 solver on the whole batch in one call
+    p64 = Problem(*med, precond_dtype=torch.complex128, **solver_cfg(args, om))
+    p64.solve(q[0:1].contiguous(), rtol=args.rtol, maxit=args.maxit)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(nsingle):
+    for s in range(32):
         p64.solve(q[s:s + 1].contiguous(), rtol=args.rtol, maxit=args.maxit)
     torch.cuda.synchronize()
-    ts = (time.perf_counter() - t0) / nsingle
+    ts = (time.perf_counter() - t0) / 32
+    t0 = time.perf_counter()
+    _, info64b, code64b = p64.solve(q, rtol=args.rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    tb64 = time.perf_counter() - t0
     del p64
     torch.cuda.empty_cache()
     out["batched_sources"] = {
-        "workload": "160^3, seed 4, 32 point sources (u_3, 4x8 lattice), float32 cycle, one batched solve",
-        "solves_per_s": 32 / tb, "iters_max": max(i["iters"] for i in info), "code": code,
+        "workload": "160^3, seed 4, 32 point sources (u_3, 4x8 lattice), float32 cycle, one batched solve "
+                    "(converged sources leave the batch at restarts)",
+        "solves_per_s": 32 / tb, "iters_min": min(iters32), "iters_max": max(iters32), "code": code,
         "baseline_fp64_single_solves_per_s": 1.0 / ts,
-        "baseline": "float64 cycle, no graphs, one source per solve (%d of the 32 sources timed)" % nsingle,
-        "speedup": ts * 32 / tb}
+        "baseline": "float64 cycle, library defaults (graphs on), one source per solve, all 32 sources",
+        "speedup": ts * 32 / tb,
+        "fp64_batched_solves_per_s": 32 / tb64, "speedup_vs_fp64_batched": tb64 / tb, "fp64_batched_code": code64b}
 
-    # 12 independent problems of uneven size, solved together (one stream each)
+    # 12 independent problems of uneven size in one batch handle (a library
+    # stream each, driven in lockstep), against the same problems solved one
+    # after another through their own handles
+    from paper_2307_03242_amd import Batch
     sizes = [64, 80, 96, 112, 128, 144, 160, 176, 192, 96, 128, 160]
-    probs, qs = [], []
+    specs, qs = [], []
     for i, nn in enumerate(sizes):
         sh = (nn, nn, nn)
         mm, md = media(sh, 100 + i)
         omi = omega_for_ppw(mm["vs"].min(), 1.0, 10)
-        st = torch.cuda.Stream()
-        with torch.cuda.stream(st):
-            probs.append(Problem(*md, precond_dtype=torch.complex64, **solver_cfg(args, omi)))
+        specs.append(dict(lam=md[0], mu=md[1], rho=md[2], precond_dtype=torch.complex64, **solver_cfg(args, omi)))
         qs.append(torch.from_numpy(point_source(sh)[None]).cuda())
+    batch = Batch(specs)
+    batch.solve(qs, rtol=args.rtol, maxit=args.maxit)   # tunes and records the graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, infos, code = Problem.solve_batch(probs, qs, rtol=args.rtol, maxit=args.maxit)
+    _, infos, code = batch.solve(qs, rtol=args.rtol, maxit=args.maxit)
     torch.cuda.synchronize()
     tc = time.perf_counter() - t0
     t0 = time.perf_counter()
-    for p, qq in zip(probs, qs):
-        p.solve(qq, rtol=args.rtol, maxit=args.maxit)
+    for i, qq in enumerate(qs):
+        batch.problem(i).solve(qq, rtol=args.rtol, maxit=args.maxit)
     torch.cuda.synchronize()
     tq = time.perf_counter() - t0
     out["uneven_batch"] = {
-        "workload": "12 problems, n = %s (seeds 100-111), 1 centred source each, float32 cycle" % sizes,
+        "workload": "12 problems, n = %s (seeds 100-111), 1 centred source each, float32 cycle, one batch handle"
+                    % sizes,
         "solves_per_s_concurrent": len(sizes) / tc, "solves_per_s_sequential": len(sizes) / tq,
+        "concurrent_over_sequential": tq / tc,
         "iters": [i[0]["iters"] for i in infos], "code": code}
-    del probs, qs
+    batch.close()
+    del batch, specs, qs
     torch.cuda.empty_cache()
 
     # FWI gradient on 128^3: 8 sources, receivers on the plane at depth 18
@@ -503,9 +546,36 @@ def main():
     resid_gbs = RESID_BYTES_F32 * n ** 3 / (resid_ms * 1e-3) / 1e9
     del x, xx, bb, rr
 
+    # the benchmark spec's cycle as written: 4-level V(1,1), float32 against
+    # float64 (one untimed solve that tunes, then one timed)
+    vcyc = {}
+    if not args.no_extras and args.cycle != "V":
+        cfgv = dict(cfg, cycle="V")
+        for name, dt in (("fp64", torch.complex128), ("fp32_precond", torch.complex64)):
+            pv = Problem(lam, mu, rho, precond_dtype=dt, **cfgv)
+            pv.solve(q, rtol=args.rtol, maxit=args.maxit)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, iv, cv = pv.solve(q, rtol=args.rtol, maxit=args.maxit)
+            torch.cuda.synchronize()
+            vcyc[name] = {"solves_per_s": 1.0 / (time.perf_counter() - t0), "iters": iv[0]["iters"],
+                          "relres": iv[0]["relres"], "code": cv}
+            del pv
+            torch.cuda.empty_cache()
+        vcyc["speedup_fp32_vs_fp64"] = vcyc["fp32_precond"]["solves_per_s"] / vcyc["fp64"]["solves_per_s"]
+
     value = 1.0 / t32
     it32 = int(np.median([i["iters"] for i in info32]))
     it64 = int(np.median([i["iters"] for i in info64]))
+    same_kernel = stencil_source_hash() == RESID_TRAFFIC_SOURCE
+    # algorithmic bytes per outer iteration on the finest level (float32
+    # cycle, per cell, from the per-unit figures): nu1 = nu2 = 1 red-black
+    # sweeps = 4 Vanka passes and 3 residuals (the first half-sweep starts
+    # from zero), 1 fused residual restriction, 1 prolongation; outer float64:
+    # the float32-input operator and classical Gram-Schmidt (j = 3 average)
+    cells = n ** 3
+    fine = {"residual_3x": 3 * RESID_BYTES_F32, "vanka_4x": 4 * 104, "restrict_residual": 76 + 4,
+            "prolong": 68, "outer_apply_f32in": 32 + 64 + 24, "gram_schmidt_j3": (2 * 3 + 3) * 64 + 64}
     out = {
         "metric": "256^3 solves/s to 1e-6 residual, FP32-precond vs FP64; stencil HBM GB/s",
         "value": value,
@@ -529,16 +599,20 @@ def main():
             "parallelism": "single GPU",
         },
         "fp64": {"solves_per_s": 1.0 / t64, "ms_per_solve": t64 * 1e3, "iters": it64,
-                 "relres": info64[-1]["relres"], "split_ms": split(info64[-1])},
+                 "relres": info64[-1]["relres"], "split_ms": split(info64[-1]),
+                 "kernels_per_iteration": info64[-1]["kernels"] / max(1, info64[-1]["iters"])},
         "fp32_precond": {"solves_per_s": value, "iters": it32, "relres": info32[-1]["relres"],
-                         "rel_diff_vs_fp64_solution": rel_diff, "split_ms": split(info32[-1])},
+                         "rel_diff_vs_fp64_solution": rel_diff, "split_ms": split(info32[-1]),
+                         "kernels_per_iteration": info32[-1]["kernels"] / max(1, info32[-1]["iters"]),
+                         "algorithmic_GB_per_iteration_finest": {k: v * cells / 1e9 for k, v in fine.items()}},
+        "vcycle_4level": vcyc,
         "speedup_fp32_vs_fp64": t64 / t32,
         "apply": {"f64_ms": apply["f64"]["ms"], "f64_GBps": apply["f64"]["gbs"],
                   "f32_ms": apply["f32"]["ms"], "f32_GBps": apply["f32"]["gbs"]},
         "roofline": {"bound": "hbm", "achieved": resid_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": resid_gbs / HBM_PEAK_GBS,
                      "traffic": (RESID_TRAFFIC_BYTES / (resid_ms * 1e-3) / 1e9
-                                 if RESID_TRAFFIC_BYTES and n == 256 else None),
+                                 if RESID_TRAFFIC_BYTES and n == 256 and same_kernel else None),
                      "kernel": "residual b - H_s x, complex64, %d^3 (%d B/cell), %.3f ms per launch"
                                % (n, RESID_BYTES_F32, resid_ms)},
     }

@@ -149,6 +149,9 @@ typedef struct {        /* (host) one record per right-hand side              */
   double t_apply_ms;    /* out: GPU time in the outer operator A z            */
   double t_orth_ms;     /* out: Gram-Schmidt passes, reductions and their     */
                         /*   host round trips                                 */
+  unsigned long long kernels; /* out: kernels the call had executed (eager
+                           launches and kernel nodes of replayed graphs; for
+                           elh_solve_batch / elh_batch_solve, all problems)   */
 } elh_solve_stats;
 
 typedef struct elh_handle elh_handle;
@@ -257,7 +260,11 @@ int elh_vcycle(elh_handle* h, int flags, int dtype, int nrhs, const void* b,
 /* Solve H u = q for nrhs right-hand sides (float64 q, u on level 0) by
  * FGMRES(opts->restart) right-preconditioned with the cycle in
  * desc->precond_dtype (Section 5: restarted flexible GMRES, relative-
- * residual stop).  u is overwritten; it is read first as the initial guess
+ * residual stop).  The Krylov bookkeeping (Hessenberg columns, Givens
+ * rotations, stop test per rhs) runs on the device; an iteration is three
+ * submissions (cycle graph, outer operator, Gram-Schmidt graph) and one wait
+ * for a small status copy.  At each restart the right-hand sides that have
+ * converged are dropped from the batch, so later cycles skip them.  u is overwritten; it is read first as the initial guess
  * when opts->zero_x0 == 0.  stats: (host) array of nrhs records, may be
  * NULL.  Returns ELH_OK when every right-hand side met rtol,
  * ELH_NOT_CONVERGED when one did not within maxit (u then holds the last
@@ -274,14 +281,41 @@ int elh_solve_adjoint(elh_handle* h, int nrhs, const void* r, void* v,
 
 /* Solve several independent problems together: problem i (handle h[i],
  * any grid size) solves nrhs[i] right-hand sides q[i] -> u[i] exactly as
- * elh_solve would.  Each problem is driven by its own host thread, so the
- * kernels of different problems overlap on the GPU when the handles were
- * created on different streams (the batched-sources / uneven-grids form of
- * the solver).  stats: (host) sum(nrhs) records in problem order, may be
- * NULL.  Returns the most severe status of all problems. */
+ * elh_solve would (same iterates, bitwise).  The calling thread drives all
+ * problems in lockstep: every FGMRES iteration enqueues each unfinished
+ * problem's cycle, outer operator and Gram-Schmidt step before it waits for
+ * any of their statuses, so the kernels of problems created on different
+ * streams overlap on the GPU; a problem leaves the lockstep when its
+ * right-hand sides have converged.  stats: (host) sum(nrhs) records in
+ * problem order, may be NULL.  Returns the most severe status of all
+ * problems (a negative one names its problem in elh_last_error). */
 int elh_solve_batch(int nprob, elh_handle* const* h, const int* nrhs,
                     const void* const* q, void* const* u,
                     const elh_solve_opts* opts, elh_solve_stats* stats);
+
+/* Batch of problems of uneven grid sizes (the batching form of the solver;
+ * the paper solves one right-hand side of one problem at a time, Section
+ * 5).  elh_batch_create builds one problem handle per desc[i] (copying
+ * lam[i], mu[i], rho[i], device float64, as elh_create does) on a stream of
+ * its own that the library creates, after the work already enqueued on
+ * `stream` (the caller's; NULL = default stream).  elh_batch_solve solves
+ * problem i's nrhs[i] right-hand sides q[i] -> u[i] as elh_solve_batch
+ * does; it waits for the caller's stream first, and later work on the
+ * caller's stream is ordered after its outputs.  elh_batch_handle returns
+ * problem i's handle (owned by the batch, valid until elh_batch_destroy)
+ * for the other entry points; elh_batch_size the number of problems.
+ * Errors: ELH_ERR_ARG (arguments; a bad desc names its problem),
+ * ELH_ERR_OOM, ELH_ERR_HIP; a failed create leaves nothing allocated. */
+typedef struct elh_batch elh_batch;
+int elh_batch_create(int nprob, const elh_desc* descs, const double* const* lam,
+                     const double* const* mu, const double* const* rho,
+                     void* stream, elh_batch** out);
+int elh_batch_size(const elh_batch* b);
+int elh_batch_handle(elh_batch* b, int i, elh_handle** h);
+int elh_batch_solve(elh_batch* b, const int* nrhs, const void* const* q,
+                    void* const* u, const elh_solve_opts* opts,
+                    elh_solve_stats* stats);
+int elh_batch_destroy(elh_batch* b);
 
 /* Parameter gradient of an FWI misfit by the adjoint state:
  *   g_m(c) = - Re sum_s v_s^H (dH/dm_c) u_s,  m in {lam, mu, rho},

@@ -8,7 +8,7 @@ raises if it has not been built.
 from ._lib import (ELH_OK, ELH_NOT_CONVERGED, ELH_C64, ELH_C128, ELH_SHIFTED,
                    ELH_ADJOINT, ElhError, load as load_library)
 
-__all__ = ["Problem", "ElhError", "load_library", "ELH_OK", "ELH_NOT_CONVERGED",
+__all__ = ["Problem", "Batch", "ElhError", "load_library", "ELH_OK", "ELH_NOT_CONVERGED",
            "ELH_C64", "ELH_C128", "ELH_SHIFTED", "ELH_ADJOINT"]
 
 
@@ -16,6 +16,9 @@ def __getattr__(name):
     if name == "Problem":
         from .api import Problem
         return Problem
+    if name == "Batch":
+        from .api import Batch
+        return Batch
     if name == "ElasticFWI":
         from .autograd import ElasticFWI
         return ElasticFWI

@@ -16,6 +16,7 @@ EXPORTED = [
     "elh_restrict_residual", "elh_prolong_add", "elh_relax", "elh_relax_noalloc", "elh_coarse_solve", "elh_kaczmarz", "elh_apply_f32in",
     "elh_vcycle", "elh_solve", "elh_solve_adjoint", "elh_solve_batch", "elh_gradient",
     "elh_level_info", "elh_stencil_choice", "elh_status_string", "elh_last_error",
+    "elh_batch_create", "elh_batch_size", "elh_batch_handle", "elh_batch_solve", "elh_batch_destroy",
 ]
 
 
@@ -46,7 +47,8 @@ class SolveStats(ctypes.Structure):
                 ("relres", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
                 ("history_cap", ctypes.c_int), ("history_len", ctypes.c_int),
                 ("t_total_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
-                ("t_apply_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double)]
+                ("t_apply_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double),
+                ("kernels", ctypes.c_ulonglong)]
 
 
 _lib = None
@@ -85,6 +87,13 @@ def load():
         "elh_gradient": [H, ip, vp, vp, vp, vp, vp],
         "elh_level_info": [H, ip, ctypes.POINTER(ctypes.c_int), dp],
         "elh_stencil_choice": [H, ip, ip, ip, ip, ip, ctypes.POINTER(ctypes.c_int)],
+        "elh_batch_create": [ip, ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                             ctypes.POINTER(ctypes.c_void_p), vp, ctypes.POINTER(ctypes.c_void_p)],
+        "elh_batch_size": [vp],
+        "elh_batch_handle": [vp, ip, ctypes.POINTER(ctypes.c_void_p)],
+        "elh_batch_solve": [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_void_p),
+                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
+        "elh_batch_destroy": [vp],
         "elh_status_string": [ip],
         "elh_last_error": [],
     }

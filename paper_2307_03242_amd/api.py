@@ -30,7 +30,48 @@ def _info(s):
     return dict(iters=s.iters, restarts=s.restarts, status=s.status, relres=s.relres,
                 history=[s.history[i] for i in range(s.history_len)] if s.history else [],
                 t_total_ms=s.t_total_ms, t_precond_ms=s.t_precond_ms, t_apply_ms=s.t_apply_ms,
-                t_orth_ms=s.t_orth_ms)
+                t_orth_ms=s.t_orth_ms, kernels=s.kernels)
+
+
+def _media(lam, mu, rho, device):
+    lam = torch.as_tensor(lam, dtype=torch.float64).to(device).contiguous()
+    mu = torch.as_tensor(mu, dtype=torch.float64).to(device).contiguous()
+    rho = torch.as_tensor(rho, dtype=torch.float64).to(device).contiguous()
+    if not (lam.shape == mu.shape == rho.shape):
+        raise ValueError("lam, mu, rho must have the same shape")
+    if lam.dim() not in (2, 3):
+        raise ValueError("media must be 2D or 3D")
+    return lam, mu, rho
+
+
+def _desc(shape, h=1.0, omega=1.0, gamma=0.01, alpha=0.3, beta=2.0 / 3.0, abl_width=0.0, abl_amp=2.0, levels=3,
+          nu1=1, nu2=1, cycle='V', damping=(0.55, 0.35, 0.25), coarse_mode="krylov", coarse_sweeps=2,
+          coarse_restart=5, coarse_maxit=10, coarse_rtol=0.0, coarse_damping=0.0, precond_dtype=torch.complex128,
+          kacz_box=4):
+    """the elh_desc of a problem on a grid of numpy shape `shape`"""
+    dim = len(shape)
+    d = L.Desc()
+    d.dim = dim
+    n = list(reversed(shape)) + [1] * (3 - dim)
+    for a in range(3):
+        d.n[a] = n[a]
+    d.h, d.omega, d.gamma, d.alpha, d.beta = h, omega, gamma, alpha, beta
+    d.abl_width, d.abl_amp = abl_width, abl_amp
+    d.levels, d.nu1, d.nu2 = levels, nu1, nu2
+    d.cycle_calls = {'V': 1, 'W': 2, 'K': 3}[cycle]
+    damping = list(damping)
+    while len(damping) < 8:
+        damping.append(damping[-1])
+    for i in range(8):
+        d.damping[i] = damping[i]
+    modes = {"krylov": L.ELH_COARSE_KRYLOV, "dense": L.ELH_COARSE_DENSE, "relax": L.ELH_COARSE_RELAX,
+             "kaczmarz": L.ELH_COARSE_KACZMARZ}
+    d.coarse_mode = modes[coarse_mode]
+    d.coarse_sweeps, d.coarse_restart, d.coarse_maxit = coarse_sweeps, coarse_restart, coarse_maxit
+    d.coarse_rtol, d.coarse_damping = coarse_rtol, coarse_damping
+    d.precond_dtype = L.ELH_C64 if precond_dtype == torch.complex64 else L.ELH_C128
+    d.kacz_box = kacz_box
+    return d
 
 
 class Problem:
@@ -49,58 +90,27 @@ class Problem:
     coarse_damping=0.8, the default when coarse_damping <= 0).
     """
 
-    def __init__(self, lam, mu, rho, h=1.0, omega=1.0, gamma=0.01, alpha=0.3,
-                 beta=2.0 / 3.0, abl_width=0.0, abl_amp=2.0, levels=3, nu1=1,
-                 nu2=1, cycle='V', damping=(0.55, 0.35, 0.25), coarse_mode="krylov",
-                 coarse_sweeps=2, coarse_restart=5, coarse_maxit=10,
-                 coarse_rtol=0.0, coarse_damping=0.0, precond_dtype=torch.complex128,
-                 kacz_box=4, device=None):
+    def __init__(self, lam, mu, rho, device=None, **params):
         self.lib = L.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        lam = torch.as_tensor(lam, dtype=torch.float64).to(self.device).contiguous()
-        mu = torch.as_tensor(mu, dtype=torch.float64).to(self.device).contiguous()
-        rho = torch.as_tensor(rho, dtype=torch.float64).to(self.device).contiguous()
-        if not (lam.shape == mu.shape == rho.shape):
-            raise ValueError("lam, mu, rho must have the same shape")
+        lam, mu, rho = _media(lam, mu, rho, self.device)
         self.shape = tuple(lam.shape)
         self.dim = len(self.shape)
-        if self.dim not in (2, 3):
-            raise ValueError("media must be 2D or 3D")
-        d = L.Desc()
-        d.dim = self.dim
-        n = list(reversed(self.shape)) + [1] * (3 - self.dim)
-        for a in range(3):
-            d.n[a] = n[a]
-        d.h, d.omega, d.gamma, d.alpha, d.beta = h, omega, gamma, alpha, beta
-        d.abl_width, d.abl_amp = abl_width, abl_amp
-        d.levels, d.nu1, d.nu2 = levels, nu1, nu2
-        d.cycle_calls = {'V': 1, 'W': 2, 'K': 3}[cycle]
-        damping = list(damping)
-        while len(damping) < 8:
-            damping.append(damping[-1])
-        for i in range(8):
-            d.damping[i] = damping[i]
-        modes = {"krylov": L.ELH_COARSE_KRYLOV, "dense": L.ELH_COARSE_DENSE, "relax": L.ELH_COARSE_RELAX,
-                 "kaczmarz": L.ELH_COARSE_KACZMARZ}
-        d.coarse_mode = modes[coarse_mode]
-        d.coarse_sweeps, d.coarse_restart, d.coarse_maxit = coarse_sweeps, coarse_restart, coarse_maxit
-        d.coarse_rtol, d.coarse_damping = coarse_rtol, coarse_damping
-        d.precond_dtype = L.ELH_C64 if precond_dtype == torch.complex64 else L.ELH_C128
-        d.kacz_box = kacz_box
-        self.desc = d
-        self.levels = levels
+        self.desc = _desc(self.shape, **params)
+        self.levels = self.desc.levels
         self._media = (lam, mu, rho)
+        self._owner = None
         self.handle = ctypes.c_void_p(0)
         with torch.cuda.device(self.device):
             st = torch.cuda.current_stream(self.device).cuda_stream
-            L.check(self.lib.elh_create(ctypes.byref(d), _ptr(lam), _ptr(mu), _ptr(rho),
+            L.check(self.lib.elh_create(ctypes.byref(self.desc), _ptr(lam), _ptr(mu), _ptr(rho),
                                         ctypes.c_void_p(st), ctypes.byref(self.handle)))
 
     # -- housekeeping ---------------------------------------------------------
     def close(self):
-        if self.handle and self.handle.value:
+        if self._owner is None and self.handle and self.handle.value:
             self.lib.elh_destroy(self.handle)
-            self.handle = ctypes.c_void_p(0)
+        self.handle = ctypes.c_void_p(0)
 
     def __del__(self):
         try:
@@ -318,3 +328,94 @@ class Problem:
         g = [torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(3)]
         L.check(self.lib.elh_gradient(self.handle, nrhs, _ptr(u), _ptr(v), _ptr(g[0]), _ptr(g[1]), _ptr(g[2])))
         return tuple(g)
+
+
+class Batch:
+    """Problems of uneven grid sizes solved together (elh_batch_*): each
+    problem gets a library-owned stream, and solve() drives all of them in
+    lockstep from the calling thread, so their kernels overlap on the GPU.
+
+    problems: list of dicts with keys lam, mu, rho (float64 tensors, numpy
+    grid shape) and the Problem keyword parameters.  problem(i) returns a
+    Problem view of problem i (owned by the batch) for the other entry
+    points."""
+
+    def __init__(self, problems, device=None):
+        self.lib = L.load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if not problems:
+            raise ValueError("a batch needs at least one problem")
+        n = len(problems)
+        self._media, descs, self._shapes = [], (L.Desc * n)(), []
+        for i, pr in enumerate(problems):
+            pr = dict(pr)
+            media = _media(pr.pop("lam"), pr.pop("mu"), pr.pop("rho"), self.device)
+            self._media.append(media)
+            self._shapes.append(tuple(media[0].shape))
+            descs[i] = _desc(self._shapes[-1], **pr)
+        self._descs = descs
+        ptrs = [(ctypes.c_void_p * n)(*[m[k].data_ptr() for m in self._media]) for k in range(3)]
+        self.handle = ctypes.c_void_p(0)
+        with torch.cuda.device(self.device):
+            st = torch.cuda.current_stream(self.device).cuda_stream
+            L.check(self.lib.elh_batch_create(n, descs, ptrs[0], ptrs[1], ptrs[2], ctypes.c_void_p(st),
+                                              ctypes.byref(self.handle)))
+        self._views = [None] * n
+
+    def __len__(self):
+        return len(self._shapes)
+
+    def problem(self, i):
+        if self._views[i] is None:
+            h = ctypes.c_void_p(0)
+            L.check(self.lib.elh_batch_handle(self.handle, i, ctypes.byref(h)))
+            p = object.__new__(Problem)
+            p.lib, p.device, p.shape = self.lib, self.device, self._shapes[i]
+            p.dim, p.desc, p.levels = len(p.shape), self._descs[i], self._descs[i].levels
+            p._media, p._owner, p.handle = self._media[i], self, h
+            self._views[i] = p
+        return self._views[i]
+
+    def solve(self, qs, restart=5, maxit=500, rtol=1e-6, store_z_fp32=None):
+        """u_i = H_i^{-1} q_i for every problem; returns (list of u, list of
+        info lists, code)."""
+        n = len(self)
+        if len(qs) != n:
+            raise ValueError("one right-hand-side batch per problem")
+        us, nr = [], []
+        for i, q in enumerate(qs):
+            if q.dtype != torch.complex128:
+                raise TypeError("right-hand sides must be complex128")
+            nr.append(self.problem(i)._vec(q, 0))
+            us.append(torch.empty_like(q))
+        if store_z_fp32 is None:
+            store_z_fp32 = all(d.precond_dtype == L.ELH_C64 for d in self._descs)
+        opts = L.SolveOpts(restart, maxit, rtol, 1, 1 if store_z_fp32 else 0)
+        stats = (L.SolveStats * sum(nr))()
+        hist = [(ctypes.c_double * maxit)() for _ in range(sum(nr))]
+        for s, h in zip(stats, hist):
+            s.history = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
+            s.history_cap = maxit
+        qp = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+        up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        code = L.check(self.lib.elh_batch_solve(self.handle, (ctypes.c_int * n)(*nr), qp, up, ctypes.byref(opts),
+                                                stats))
+        infos, k = [], 0
+        for r in nr:
+            infos.append([_info(s) for s in stats[k:k + r]])
+            k += r
+        return us, infos, code
+
+    def close(self):
+        if self.handle and self.handle.value:
+            for v in self._views:
+                if v is not None:
+                    v.handle = ctypes.c_void_p(0)
+            self.lib.elh_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

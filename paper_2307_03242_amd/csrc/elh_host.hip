@@ -12,9 +12,10 @@
 #include <atomic>
 #include <chrono>
 #include <complex>
+#include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
-#include <thread>
 #include <vector>
 
 #include "../../include/elh.h"
@@ -22,6 +23,8 @@
 
 using namespace elh;
 typedef std::complex<double> zd;
+
+std::atomic<unsigned long long> elh::g_kernels{0};
 
 static thread_local char g_err[512] = "";
 
@@ -92,6 +95,7 @@ struct LevelData {
 // Krylov workspace for one (level, precision, Z precision) combination.
 struct KrylovWS {
   DevBuf V, Z, w, t;
+  DevBuf B, X;  // outer solve: right-hand sides and iterates of the packed (still active) rhs
 };
 
 // Hybrid Kaczmarz coarsest solve: rows of the Schur complement in the slot
@@ -106,10 +110,12 @@ struct KaczData {
 };
 
 struct GraphEntry {
+  int kind = 0, step = 0;  // 0: preconditioner cycle; 1: outer Gram-Schmidt step `step`
   int prec, adj, nrhs;
   const void* in;
   void* out;
   uint64_t gen;
+  unsigned long long nkern = 0;  // kernel nodes
   hipGraphExec_t exec;
 };
 
@@ -120,7 +126,10 @@ struct elh_handle {
   LevelData lv[8];
   KrylovWS kout[2], kin[2];  // outer (level 0, f64; Z f64/f32), inner (coarsest; f64/f32)
   DevBuf part, dots, coef, tmpvec;
-  DevBuf gstate, gpart, gdots, gnrm, gcoef, gscale, ones;  // device-resident GMRES
+  DevBuf gstate, gpart, gdots, gnrm, gcoef, gscale, ones;  // device-resident GMRES (coarsest level)
+  DevBuf ostate, opart, odots, ocoef, ostat, opar;           // device-resident outer FGMRES
+  double* hstat = nullptr;  // pinned host copy of ostat
+  double* hpar = nullptr;   // pinned staging of opar
   DevBuf dq64, dq32;                                        // dense coarsest inverse (Q = inv(H_s^T))
   KaczData kz;                                              // hybrid Kaczmarz coarsest solve
   int64_t dn = 0;
@@ -354,8 +363,17 @@ extern "C" int elh_create(const elh_desc* desc, const double* lam, const double*
     elh_destroy(H);
     return fail(ELH_ERR_HIP, "stream creation failed");
   }
+  if (ensure(H->ostate, (size_t)MAXRHS_KRYLOV * GO_STRIDE * 8) ||
+      ensure(H->opart, (size_t)MAXRHS_KRYLOV * 512 * MAXDOT * 2 * 8) || ensure(H->odots, MAXRHS_KRYLOV * MAXDOT * 16) ||
+      ensure(H->ocoef, MAXRHS_KRYLOV * MAXDOT * 16) || ensure(H->ostat, MAXRHS_KRYLOV * 4 * 8) ||
+      ensure(H->opar, MAXRHS_KRYLOV * 4 * 8)) {
+    elh_destroy(H);
+    return ELH_ERR_OOM;
+  }
   if (hipHostMalloc((void**)&H->hdots, MAXRHS_KRYLOV * MAXDOT * 16, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&H->hcoef, MAXRHS_KRYLOV * MAXDOT * 16, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&H->hcoef, MAXRHS_KRYLOV * MAXDOT * 16, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&H->hstat, MAXRHS_KRYLOV * 4 * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&H->hpar, MAXRHS_KRYLOV * 4 * 8, hipHostMallocDefault) != hipSuccess) {
     elh_destroy(H);
     return fail(ELH_ERR_OOM, "pinned host allocation failed");
   }
@@ -397,11 +415,12 @@ extern "C" int elh_destroy(elh_handle* H) {
   }
   for (int p = 0; p < 2; ++p) {
     KrylovWS* ws[2] = {&H->kout[p], &H->kin[p]};
-    for (auto* w : ws) { release(w->V); release(w->Z); release(w->w); release(w->t); }
+    for (auto* w : ws) { release(w->V); release(w->Z); release(w->w); release(w->t); release(w->B); release(w->X); }
   }
   release(H->part); release(H->dots); release(H->coef); release(H->tmpvec);
   release(H->gstate); release(H->gpart); release(H->gdots); release(H->gnrm); release(H->gcoef);
   release(H->gscale); release(H->ones); release(H->dq64); release(H->dq32);
+  release(H->ostate); release(H->opart); release(H->odots); release(H->ocoef); release(H->ostat); release(H->opar);
   for (int a = 0; a < 2; ++a) {
     for (int p = 0; p < 2; ++p) { release(H->kz.val[a][p]); release(H->kz.inv[a][p]); }
     release(H->kz.tab[a]); release(H->kz.dl[a]); release(H->kz.gptr[a]); release(H->kz.gent[a]);
@@ -415,6 +434,8 @@ extern "C" int elh_destroy(elh_handle* H) {
     if (e) (void)hipEventDestroy(e);
   if (H->hdots) (void)hipHostFree(H->hdots);
   if (H->hcoef) (void)hipHostFree(H->hcoef);
+  if (H->hstat) (void)hipHostFree(H->hstat);
+  if (H->hpar) (void)hipHostFree(H->hpar);
   delete H;
   return 0;
 }
@@ -1476,12 +1497,15 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
 // sequences with no host synchronisation are captured (the cycle with a
 // fixed-budget coarse solve).
 template <typename Fn>
-static int run_graph(elh_handle* H, int prec, int adj, int nrhs, const void* in, void* out, Fn fn) {
+static int run_graph(elh_handle* H, int prec, int adj, int nrhs, const void* in, void* out, Fn fn, int kind = 0,
+                     int step = 0) {
   for (size_t i = 0; i < H->graphs.size(); ++i) {
     GraphEntry& g = H->graphs[i];
-    if (g.prec == prec && g.adj == adj && g.nrhs == nrhs && g.in == in && g.out == out) {
+    if (g.kind == kind && g.step == step && g.prec == prec && g.adj == adj && g.nrhs == nrhs && g.in == in &&
+        g.out == out) {
       if (g.gen == g_alloc_gen) {
         HIPCHK(hipGraphLaunch(g.exec, H->st));
+        g_kernels.fetch_add(g.nkern, std::memory_order_relaxed);
         return 0;
       }
       (void)hipGraphExecDestroy(g.exec);
@@ -1504,6 +1528,21 @@ static int run_graph(elh_handle* H, int prec, int adj, int nrhs, const void* in,
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(H->cap, &graph);
   H->st = saved;
+  // the recorded launches did not run: take them off the count
+  unsigned long long nkern = 0;
+  if (graph) {
+    size_t nn = 0;
+    std::vector<hipGraphNode_t> nodes;
+    if (hipGraphGetNodes(graph, nullptr, &nn) == hipSuccess && nn > 0) {
+      nodes.resize(nn);
+      if (hipGraphGetNodes(graph, nodes.data(), &nn) == hipSuccess)
+        for (size_t i = 0; i < nn; ++i) {
+          hipGraphNodeType t;
+          if (hipGraphNodeGetType(nodes[i], &t) == hipSuccess && t == hipGraphNodeTypeKernel) ++nkern;
+        }
+    }
+    g_kernels.fetch_sub(nkern, std::memory_order_relaxed);
+  }
   if (rc != 0 || e != hipSuccess || gen != g_alloc_gen) {
     if (graph) (void)hipGraphDestroy(graph);
     if (rc != 0) return rc > 0 ? fail(ELH_ERR_HIP, "launch failed during graph capture") : rc;
@@ -1511,7 +1550,9 @@ static int run_graph(elh_handle* H, int prec, int adj, int nrhs, const void* in,
     return 0;  // allocation changed while recording: keep running eagerly
   }
   GraphEntry g;
+  g.kind = kind; g.step = step;
   g.prec = prec; g.adj = adj; g.nrhs = nrhs; g.in = in; g.out = out; g.gen = gen;
+  g.nkern = nkern;
   e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(ELH_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
@@ -1522,6 +1563,315 @@ static int run_graph(elh_handle* H, int prec, int adj, int nrhs, const void* in,
 static bool graphs_ok(const elh_handle* H) {
   return H->use_graphs && !((H->d.coarse_mode == ELH_COARSE_KRYLOV || H->d.coarse_mode == ELH_COARSE_KACZMARZ) &&
                              H->d.coarse_rtol > 0);
+}
+
+// ---------------------------------------------------------------------------
+// Outer flexible GMRES with its bookkeeping on the device (the solve entry
+// points).  Right-preconditioned FGMRES(m) from x0 (zero or the caller's),
+// relative-residual stop per rhs, classical Gram-Schmidt on the unnormalised
+// basis (see gmres() above for the scaling), complex Givens rotations.  One
+// iteration is three submissions with no host work between them -- the
+// preconditioner cycle (a replayed hipGraph), the outer operator, and the
+// Gram-Schmidt step (dots, Hessenberg column, update and norm, rotation and
+// stop test, copy of the per-rhs status to the host; a replayed hipGraph per
+// step index) -- and the host waits once per iteration, for the status.  At a
+// restart the right-hand sides that have converged leave: the rest are packed
+// into leading slots, so later cycles and operator applies skip them.  The
+// solve is a resumable state machine, so that one host thread can drive
+// several problems in lockstep (elh_solve_batch).
+// ---------------------------------------------------------------------------
+struct OuterOps {
+  std::function<int(const void* v, void* z, int n)> M;                  // z = M v
+  std::function<int(const void* z, void* w, int n)> AZ;                 // w = A z
+  std::function<int(const void* x, const void* b, void* r, int n)> AR;  // r = b - A x
+};
+
+struct OuterSolve {
+  elh_handle* H = nullptr;
+  int nrhs = 0, m = 5, maxit = 1;
+  double rtol = 0;
+  bool x0 = false, z32 = false;
+  int64_t len = 0;
+  const cx<double>* q = nullptr;
+  cx<double>* u = nullptr;
+  OuterOps ops;
+  KrylovWS* ws = nullptr;
+  void* cyc_in = nullptr;  // float32 copy of v_j when the cycle reads float32 (z32)
+  // packed rhs: slot i holds rhs map[i] (b, x in bp / xp, stride len)
+  int np = 0;
+  std::vector<int> map;
+  const cx<double>* bp = nullptr;
+  cx<double>* xp = nullptr;
+  bool own = false;
+  std::vector<double> nb, beta;
+  std::vector<char> active, live;  // active: per rhs; live: per slot in the current restart
+  GmresStats gs;
+  std::unique_ptr<PhaseTimer> tm;
+  int iters = 0, j = 0;
+  bool in_restart = false, done = false;
+  int64_t vstr() const { return (int64_t)np * len; }
+  cx<double>* V(int i) const { return (cx<double>*)ws->V.p + i * vstr(); }
+  void* Z(int i) const { return (char*)ws->Z.p + i * vstr() * (z32 ? 8 : 16); }
+};
+
+// ||V_0||^2 (or ||q||^2) per packed slot -> host (synchronises)
+static int os_norms(OuterSolve& S, const void* v, int n, std::vector<double>& out) {
+  elh_handle* H = S.H;
+  std::vector<zd> d;
+  CHK((launch_multidot<cx<double>, cx<double>>(1, v, 0, S.len, v, S.len, S.len, n, (double*)H->part.p,
+                                               (double*)H->dots.p, H->st)));
+  CHK(fetch_dots(H, n, 1, d));
+  out.resize(n);
+  for (int i = 0; i < n; ++i) out[i] = sqrt(d[i].real());
+  return 0;
+}
+
+static int os_begin(OuterSolve& S) {
+  elh_handle* H = S.H;
+  const int n = S.nrhs;
+  const size_t vb = (size_t)n * S.len * 16;
+  if (ensure(S.ws->V, vb * (S.m + 1)) || ensure(S.ws->Z, (size_t)n * S.len * (S.z32 ? 8 : 16) * S.m))
+    return ELH_ERR_OOM;
+  S.np = n;
+  S.map.resize(n);
+  for (int i = 0; i < n; ++i) S.map[i] = i;
+  S.bp = S.q;
+  S.xp = S.u;
+  S.own = false;
+  CHK(os_norms(S, S.q, n, S.nb));
+  if (S.x0) {
+    CHK(S.ops.AR(S.u, S.q, S.V(0), n));
+    CHK(os_norms(S, S.V(0), n, S.beta));
+  } else {
+    CHK(launch_zero(S.u, vb, H->st));
+    HIPCHK(hipMemcpyAsync(S.V(0), S.q, vb, hipMemcpyDeviceToDevice, H->st));
+    S.beta = S.nb;
+  }
+  S.gs.iters.assign(n, 0);
+  S.gs.restarts.assign(n, 0);
+  S.gs.status.assign(n, ELH_NOT_CONVERGED);
+  S.gs.relres.assign(n, 1.0);
+  S.gs.history.assign(n, std::vector<double>());
+  S.tm.reset(new PhaseTimer(S.gs.timing));
+  S.active.assign(n, 0);
+  int nact = 0;
+  for (int s = 0; s < n; ++s) {
+    if (!isfinite(S.nb[s]) || !isfinite(S.beta[s])) return fail(ELH_ERR_NUMERIC, "non-finite initial residual (rhs %d)", s);
+    if (!(S.nb[s] > 0)) {
+      // q = 0: the solution is 0 (an initial guess is discarded)
+      S.gs.status[s] = ELH_OK;
+      S.gs.relres[s] = 0.0;
+      if (S.x0) CHK(launch_zero(S.u + (int64_t)s * S.len, S.len * 16, H->st));
+    } else {
+      S.gs.relres[s] = S.beta[s] / S.nb[s];
+      S.active[s] = S.gs.relres[s] > S.rtol && S.beta[s] > 0;
+      if (!S.active[s]) S.gs.status[s] = ELH_OK;
+    }
+    nact += S.active[s];
+  }
+  S.iters = 0;
+  S.done = nact == 0;
+  S.in_restart = false;
+  return 0;
+}
+
+// pack the active rhs into the leading slots (b, x and the restart's first
+// basis vector); rhs that leave have their iterate written back to u
+static int os_compact(OuterSolve& S) {
+  elh_handle* H = S.H;
+  std::vector<int> keep;
+  for (int i = 0; i < S.np; ++i)
+    if (S.active[S.map[i]]) keep.push_back(i);
+  if ((int)keep.size() == S.np) return 0;
+  const size_t vb1 = (size_t)S.len * 16;
+  if (!S.own) {
+    if (ensure(S.ws->B, vb1 * S.nrhs) || ensure(S.ws->X, vb1 * S.nrhs)) return ELH_ERR_OOM;
+    cx<double>* B = (cx<double>*)S.ws->B.p;
+    cx<double>* X = (cx<double>*)S.ws->X.p;
+    for (size_t k = 0; k < keep.size(); ++k) {
+      const int i = keep[k], s = S.map[i];
+      HIPCHK(hipMemcpyAsync(B + k * S.len, S.q + (int64_t)s * S.len, vb1, hipMemcpyDeviceToDevice, H->st));
+      HIPCHK(hipMemcpyAsync(X + k * S.len, S.u + (int64_t)s * S.len, vb1, hipMemcpyDeviceToDevice, H->st));
+    }
+    S.bp = B;
+    S.xp = X;
+    S.own = true;
+  } else {
+    cx<double>* B = (cx<double>*)S.ws->B.p;
+    cx<double>* X = (cx<double>*)S.ws->X.p;
+    for (int i = 0; i < S.np; ++i)
+      if (!S.active[S.map[i]])
+        HIPCHK(hipMemcpyAsync(S.u + (int64_t)S.map[i] * S.len, X + (int64_t)i * S.len, vb1, hipMemcpyDeviceToDevice,
+                              H->st));
+    for (size_t k = 0; k < keep.size(); ++k)
+      if ((int)k != keep[k]) {
+        HIPCHK(hipMemcpyAsync(B + k * S.len, B + keep[k] * S.len, vb1, hipMemcpyDeviceToDevice, H->st));
+        HIPCHK(hipMemcpyAsync(X + k * S.len, X + keep[k] * S.len, vb1, hipMemcpyDeviceToDevice, H->st));
+      }
+  }
+  // the first basis vector (true residual of the last restart), slot stride len
+  cx<double>* V0 = (cx<double>*)S.ws->V.p;
+  for (size_t k = 0; k < keep.size(); ++k)
+    if ((int)k != keep[k])
+      HIPCHK(hipMemcpyAsync(V0 + k * S.len, V0 + keep[k] * S.len, vb1, hipMemcpyDeviceToDevice, H->st));
+  std::vector<int> nm;
+  for (int i : keep) nm.push_back(S.map[i]);
+  S.map = nm;
+  S.np = (int)keep.size();
+  return 0;
+}
+
+static int os_restart_begin(OuterSolve& S) {
+  elh_handle* H = S.H;
+  CHK(os_compact(S));
+  const int n = S.np;
+  for (int i = 0; i < n; ++i) {
+    const int s = S.map[i];
+    H->hpar[4 * i] = S.active[s] ? 1.0 : 0.0;
+    H->hpar[4 * i + 1] = S.nb[s];
+    H->hpar[4 * i + 2] = S.rtol;
+    H->hpar[4 * i + 3] = 0.0;
+  }
+  HIPCHK(hipMemcpyAsync(H->opar.p, H->hpar, (size_t)n * 32, hipMemcpyHostToDevice, H->st));
+  double* part = (double*)H->opart.p;
+  const bool fn = n * 2 <= FUSE_VALS;
+  CHK((launch_multidot<cx<double>, cx<double>>(1, S.V(0), 0, S.len, S.V(0), S.len, S.len, n, part,
+                                               fn ? nullptr : (double*)H->odots.p, H->st)));
+  CHK(launch_go_start(n, fn ? nullptr : (double*)H->odots.p, fn ? part : nullptr,
+                      multidot_blocks(1, S.len, FUSE_BLOCKS), (const double*)H->opar.p, (double*)H->ostate.p,
+                      (double*)H->ostat.p, H->st));
+  if (S.z32) CHK((launch_scale_copy<cx<double>, cx<float>>(nullptr, S.V(0), S.len, S.cyc_in, S.len, S.len, n, H->st)));
+  S.live.assign(n, 0);
+  for (int i = 0; i < n; ++i) S.live[i] = S.active[S.map[i]] && S.beta[S.map[i]] > 0;
+  S.j = 0;
+  S.in_restart = true;
+  // the pinned parameter block is rewritten at the next restart, after the
+  // synchronisation that ends this one
+  return 0;
+}
+
+// the Gram-Schmidt step j: dots, Hessenberg column, update with its norm
+// (and the float32 copy feeding the next cycle), rotation and stop test,
+// status to the host
+static int os_gs_step(OuterSolve& S) {
+  elh_handle* H = S.H;
+  const int n = S.np, j = S.j;
+  const int64_t vs = S.vstr();
+  cx<double>* W = S.V(j + 1);
+  double* part = (double*)H->opart.p;
+  const bool fd = n * 2 * (j + 1) <= FUSE_VALS, fn = n * 2 <= FUSE_VALS;
+  CHK((launch_multidot<cx<double>, cx<double>>(j + 1, S.V(0), vs, S.len, W, S.len, S.len, n, part,
+                                               fd ? nullptr : (double*)H->odots.p, H->st)));
+  CHK(launch_go_hcol(n, j, fd ? nullptr : (double*)H->odots.p, fd ? part : nullptr,
+                     multidot_blocks(j + 1, S.len, FUSE_BLOCKS), (double*)H->ostate.p, (double*)H->ocoef.p, H->st));
+  if (S.z32)
+    CHK((launch_axpy_norm<cx<double>, cx<float>>(j + 1, (const double*)H->ocoef.p, S.V(0), vs, S.len, W, S.len,
+                                                 S.cyc_in, S.len, S.len, n, part,
+                                                 fn ? nullptr : (double*)H->odots.p, H->st)));
+  else
+    CHK((launch_axpy_norm<cx<double>, cx<double>>(j + 1, (const double*)H->ocoef.p, S.V(0), vs, S.len, W, S.len,
+                                                  nullptr, S.len, S.len, n, part,
+                                                  fn ? nullptr : (double*)H->odots.p, H->st)));
+  CHK(launch_go_rotate(n, j, fn ? nullptr : (double*)H->odots.p, fn ? part : nullptr, norm_blocks(S.len, FUSE_BLOCKS),
+                       (double*)H->ostate.p, (double*)H->ostat.p, H->st));
+  HIPCHK(hipMemcpyAsync(H->hstat, H->ostat.p, (size_t)n * 32, hipMemcpyDeviceToHost, H->st));
+  return 0;
+}
+
+// enqueue iteration j of the current restart (no host synchronisation)
+static int os_iter_enqueue(OuterSolve& S) {
+  elh_handle* H = S.H;
+  PhaseTimer& tm = *S.tm;
+  const int n = S.np, j = S.j;
+  tm.mark(0, H->st);
+  CHK(S.ops.M(S.z32 ? (const void*)S.cyc_in : (const void*)S.V(j), S.Z(j), n));
+  tm.mark(1, H->st);
+  CHK(S.ops.AZ(S.Z(j), S.V(j + 1), n));
+  tm.mark(2, H->st);
+  auto step = [&]() { return os_gs_step(S); };
+  CHK(H->use_graphs ? run_graph(H, S.z32 ? 1 : 0, 0, n, S.Z(0), S.V(0), step, 1, j) : step());
+  tm.mark(3, H->st);
+  return 0;
+}
+
+// wait for iteration j's status; ends the restart when every packed rhs has
+// stopped, the budget is spent or the basis is full
+static int os_restart_end(OuterSolve& S);
+static int os_iter_finish(OuterSolve& S) {
+  elh_handle* H = S.H;
+  HIPCHK(hipStreamSynchronize(H->st));
+  S.gs.t_precond += S.tm->span(0, 1);
+  S.gs.t_apply += S.tm->span(1, 2);
+  S.gs.t_orth += S.tm->span(2, 3);
+  ++S.iters;
+  bool any = false;
+  for (int i = 0; i < S.np; ++i) {
+    const double* st = H->hstat + 4 * i;
+    const int s = S.map[i];
+    if (st[3] != 0.0) return fail(ELH_ERR_NUMERIC, "non-finite norm in GMRES (rhs %d)", s);
+    if (!S.live[i]) continue;
+    S.gs.iters[s]++;
+    S.gs.history[s].push_back(st[2]);
+    S.live[i] = st[0] != 0.0;
+    any = any || S.live[i];
+  }
+  ++S.j;
+  if (!any || S.iters >= S.maxit || S.j == S.m) return os_restart_end(S);
+  return 0;
+}
+
+// x += Z y per rhs, then the true residual (the next restart's first basis
+// vector), its norm (synchronises) and the stop test
+static int os_restart_end(OuterSolve& S) {
+  elh_handle* H = S.H;
+  const int n = S.np, k = S.j;
+  CHK(launch_go_update(n, k, (const double*)H->ostate.p, (double*)H->ocoef.p, H->st));
+  if (S.z32)
+    CHK((launch_multiaxpy<cx<float>, cx<double>>(k, (const double*)H->ocoef.p, S.Z(0), S.vstr(), S.len, S.xp, S.len,
+                                                 S.len, n, H->st)));
+  else
+    CHK((launch_multiaxpy<cx<double>, cx<double>>(k, (const double*)H->ocoef.p, S.Z(0), S.vstr(), S.len, S.xp,
+                                                  S.len, S.len, n, H->st)));
+  CHK(S.ops.AR(S.xp, S.bp, S.V(0), n));
+  std::vector<double> bn;
+  CHK(os_norms(S, S.V(0), n, bn));
+  int nact = 0;
+  for (int i = 0; i < n; ++i) {
+    const int s = S.map[i];
+    if (!S.active[s]) continue;
+    S.gs.restarts[s]++;
+    S.beta[s] = bn[i];
+    if (!isfinite(bn[i])) return fail(ELH_ERR_NUMERIC, "non-finite residual (rhs %d)", s);
+    S.gs.relres[s] = bn[i] / S.nb[s];
+    if (S.gs.relres[s] <= S.rtol || bn[i] == 0) {
+      S.active[s] = 0;
+      S.gs.status[s] = ELH_OK;
+    }
+    nact += S.active[s];
+  }
+  S.in_restart = false;
+  S.done = nact == 0 || S.iters >= S.maxit;
+  return 0;
+}
+
+// write the packed iterates back to u
+static int os_finish(OuterSolve& S) {
+  if (!S.own) return 0;
+  const cx<double>* X = (const cx<double>*)S.ws->X.p;
+  for (int i = 0; i < S.np; ++i)
+    HIPCHK(hipMemcpyAsync(S.u + (int64_t)S.map[i] * S.len, X + (int64_t)i * S.len, (size_t)S.len * 16,
+                          hipMemcpyDeviceToDevice, S.H->st));
+  return 0;
+}
+
+static int os_run(OuterSolve& S) {
+  CHK(os_begin(S));
+  while (!S.done) {
+    if (!S.in_restart) CHK(os_restart_begin(S));
+    CHK(os_iter_enqueue(S));
+    CHK(os_iter_finish(S));
+  }
+  return os_finish(S);
 }
 
 // ---------------------------------------------------------------------------
@@ -1678,8 +2028,10 @@ extern "C" int elh_vcycle(elh_handle* H, int flags, int dtype, int nrhs, const v
 // ---------------------------------------------------------------------------
 // C ABI: solves
 // ---------------------------------------------------------------------------
-static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u, const elh_solve_opts* opts,
-                      elh_solve_stats* stats) {
+// Validate a solve and set up its state (operators of the problem's
+// precision mode, workspaces); nothing is launched.
+static int os_setup(elh_handle* H, bool adj, int nrhs, const void* q, void* u, const elh_solve_opts* opts, bool timing,
+                    OuterSolve& S) {
   int rc = check_common(H, 0, ELH_C128, nrhs);
   if (rc) return rc;
   if (!q || !u || q == u) return fail(ELH_ERR_ARG, "q and u must be distinct non-NULL pointers");
@@ -1692,65 +2044,72 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
   if (opts->store_z_fp32 != 0 && opts->store_z_fp32 != 1) return fail(ELH_ERR_ARG, "store_z_fp32 must be 0 or 1");
   if (opts->store_z_fp32 && H->d.precond_dtype != ELH_C64)
     return fail(ELH_ERR_ARG, "store_z_fp32 needs the float32 cycle (precond_dtype ELH_C64)");
-  const bool x0 = opts->zero_x0 == 0;
   const int pprec = prec_of(H->d.precond_dtype);
   if (ensure_cycle_bufs(H, pprec, nrhs)) return ELH_ERR_OOM;
   LevelData& L0 = H->lv[0];
   const int64_t len = L0.vs;
-  GmresStats gs;
-  gs.timing = stats != nullptr;
-  const auto wall0 = std::chrono::steady_clock::now();
-  auto AR = [&](const void* xi, const void* bi, void* ro) {
-    return op_apply<double>(H, 0, false, adj, xi, bi, ro, nrhs);
+  S.H = H;
+  S.nrhs = nrhs;
+  S.m = opts->restart;
+  S.maxit = opts->maxit;
+  S.rtol = opts->rtol;
+  S.x0 = opts->zero_x0 == 0;
+  S.len = len;
+  S.q = (const cx<double>*)q;
+  S.u = (cx<double>*)u;
+  S.gs.timing = timing;
+  S.ops.AR = [H, adj](const void* xi, const void* bi, void* ro, int n) {
+    return op_apply<double>(H, 0, false, adj, xi, bi, ro, n);
   };
   if (pprec == 0) {
-    auto AZ = [&](const void* zi, void* wo) { return op_apply<double>(H, 0, false, adj, zi, nullptr, wo, nrhs); };
-    auto M = [&](const void* v, void* z) {
-      auto fn = [&]() { return cycle<double>(H, 0, adj, v, z, nrhs); };
-      return graphs_ok(H) ? run_graph(H, 0, adj, nrhs, v, z, fn) : fn();
+    S.ws = &H->kout[0];
+    S.ops.AZ = [H, adj](const void* zi, void* wo, int n) { return op_apply<double>(H, 0, false, adj, zi, nullptr, wo, n); };
+    S.ops.M = [H, adj](const void* v, void* z, int n) {
+      auto fn = [&]() { return cycle<double>(H, 0, adj, v, z, n); };
+      return graphs_ok(H) ? run_graph(H, 0, adj, n, v, z, fn) : fn();
     };
-    rc = gmres<double, double>(H, H->kout[0], len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol,
-                               gs, nullptr, x0);
   } else if (!opts->store_z_fp32) {
     // float32 cycle, z_j widened to complex128: the cycle reads a float32
     // copy of v_j and writes float32 into a level-0 work buffer, which is
     // widened into Z (exact); everything else is the float64 solve
-    LevelData& W = H->lv[0];
-    auto M = [&](const void* v, void* z) {
-      CHK((launch_scale_copy<cx<double>, cx<float>>(nullptr, v, len, W.b[1].p, len, len, nrhs, H->st)));
-      auto fn = [&]() { return cycle<float>(H, 0, adj, W.b[1].p, W.x[1].p, nrhs); };
-      CHK(graphs_ok(H) ? run_graph(H, 1, adj, nrhs, W.b[1].p, W.x[1].p, fn) : fn());
-      return launch_scale_copy<cx<float>, cx<double>>(nullptr, W.x[1].p, len, z, len, len, nrhs, H->st);
+    S.ws = &H->kout[0];
+    LevelData* W = &H->lv[0];
+    S.ops.M = [H, adj, W, len](const void* v, void* z, int n) {
+      CHK((launch_scale_copy<cx<double>, cx<float>>(nullptr, v, len, W->b[1].p, len, len, n, H->st)));
+      auto fn = [&]() { return cycle<float>(H, 0, adj, W->b[1].p, W->x[1].p, n); };
+      CHK(graphs_ok(H) ? run_graph(H, 1, adj, n, W->b[1].p, W->x[1].p, fn) : fn());
+      return launch_scale_copy<cx<float>, cx<double>>(nullptr, W->x[1].p, len, z, len, len, n, H->st);
     };
-    auto AZ = [&](const void* zi, void* wo) { return op_apply<double>(H, 0, false, adj, zi, nullptr, wo, nrhs); };
-    rc = gmres<double, double>(H, H->kout[0], len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol,
-                               gs, nullptr, x0);
+    S.ops.AZ = [H, adj](const void* zi, void* wo, int n) { return op_apply<double>(H, 0, false, adj, zi, nullptr, wo, n); };
   } else {
     // float32 cycle (Section 5.3 mixed precision): the cycle reads a
     // float32 copy of the basis vector (written by the Gram-Schmidt pass)
     // and writes z_j in float32; the outer operator reads z_j in float32
     // and computes in float64; all Krylov state stays float64.
-    KrylovWS& ws = H->kout[1];
-    auto M = [&](const void* v, void* z) {
-      auto fn = [&]() { return cycle<float>(H, 0, adj, v, z, nrhs); };
-      return graphs_ok(H) ? run_graph(H, 1, adj, nrhs, v, z, fn) : fn();
+    KrylovWS* ws = &H->kout[1];
+    S.ws = ws;
+    S.z32 = true;
+    S.cyc_in = L0.b[1].p;
+    S.ops.M = [H, adj](const void* v, void* z, int n) {
+      auto fn = [&]() { return cycle<float>(H, 0, adj, v, z, n); };
+      return graphs_ok(H) ? run_graph(H, 1, adj, n, v, z, fn) : fn();
     };
-    const bool direct = H->d.dim == 3 && !adj && L0.fs >= 16 * 16 * 16 &&
-                        L0.fs * 16 <= (int64_t)0x7fffffff;
-    if (!direct && ensure(ws.t, (size_t)nrhs * len * 16)) return ELH_ERR_OOM;
-    auto AZ = [&](const void* zi, void* wo) {
-      if (direct) return op_apply_f32in(H, adj, zi, wo, nrhs);
-      CHK((launch_scale_copy<cx<float>, cx<double>>(nullptr, zi, len, ws.t.p, len, len, nrhs, H->st)));
-      return op_apply<double>(H, 0, false, adj, ws.t.p, nullptr, wo, nrhs);
+    const bool direct = H->d.dim == 3 && !adj && L0.fs >= 16 * 16 * 16 && L0.fs * 16 <= (int64_t)0x7fffffff;
+    if (!direct && ensure(ws->t, (size_t)nrhs * len * 16)) return ELH_ERR_OOM;
+    S.ops.AZ = [H, adj, direct, ws, len](const void* zi, void* wo, int n) {
+      if (direct) return op_apply_f32in(H, adj, zi, wo, n);
+      CHK((launch_scale_copy<cx<float>, cx<double>>(nullptr, zi, len, ws->t.p, len, len, n, H->st)));
+      return op_apply<double>(H, 0, false, adj, ws->t.p, nullptr, wo, n);
     };
-    rc = gmres<double, float>(H, ws, len, nrhs, AZ, AR, M, q, u, opts->restart, opts->maxit, opts->rtol, gs,
-                              L0.b[1].p, x0);
   }
-  if (rc < 0) return rc;
-  const double wall =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+  return 0;
+}
+
+// statistics of a finished solve; returns the most severe per-rhs status
+static int os_report(const OuterSolve& S, double wall, unsigned long long kernels, elh_solve_stats* stats) {
   int worst = ELH_OK;
-  for (int s = 0; s < nrhs; ++s) {
+  const GmresStats& gs = S.gs;
+  for (int s = 0; s < S.nrhs; ++s) {
     if (stats) {
       stats[s].iters = gs.iters[s];
       stats[s].restarts = gs.restarts[s];
@@ -1764,10 +2123,24 @@ static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u,
       stats[s].t_precond_ms = gs.t_precond;
       stats[s].t_apply_ms = gs.t_apply;
       stats[s].t_orth_ms = gs.t_orth;
+      stats[s].kernels = kernels;
     }
     if (gs.status[s] != ELH_OK) worst = gs.status[s];
   }
   return worst;
+}
+
+static int solve_impl(elh_handle* H, bool adj, int nrhs, const void* q, void* u, const elh_solve_opts* opts,
+                      elh_solve_stats* stats) {
+  const auto wall0 = std::chrono::steady_clock::now();
+  const unsigned long long k0 = g_kernels.load();
+  OuterSolve S;
+  int rc = os_setup(H, adj, nrhs, q, u, opts, stats != nullptr, S);
+  if (rc) return rc;
+  rc = os_run(S);
+  if (rc < 0) return rc;
+  const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+  return os_report(S, wall, g_kernels.load() - k0, stats);
 }
 
 extern "C" int elh_solve(elh_handle* H, int nrhs, const void* q, void* u, const elh_solve_opts* opts,
@@ -1780,8 +2153,13 @@ extern "C" int elh_solve_adjoint(elh_handle* H, int nrhs, const void* r, void* v
   return solve_impl(H, true, nrhs, r, v, opts, stats);
 }
 
-extern "C" int elh_solve_batch(int nprob, elh_handle* const* hs, const int* nrhs, const void* const* q,
-                               void* const* u, const elh_solve_opts* opts, elh_solve_stats* stats) {
+// Several problems in lockstep from one host thread: every iteration
+// enqueues each unfinished problem's cycle, operator and Gram-Schmidt step on
+// its own stream before waiting for any status, so the problems' kernels run
+// side by side on the GPU; a problem leaves the lockstep when its rhs have
+// converged.
+static int batch_drive(int nprob, elh_handle* const* hs, const int* nrhs, const void* const* q, void* const* u,
+                       const elh_solve_opts* opts, elh_solve_stats* stats) {
   if (nprob < 1 || !hs || !nrhs || !q || !u || !opts) return fail(ELH_ERR_ARG, "invalid batch arguments");
   std::vector<int> off(nprob + 1, 0);
   for (int i = 0; i < nprob; ++i) {
@@ -1791,25 +2169,159 @@ extern "C" int elh_solve_batch(int nprob, elh_handle* const* hs, const int* nrhs
       if (hs[j] == hs[i]) return fail(ELH_ERR_ARG, "handle %d appears twice", i);
     off[i + 1] = off[i] + nrhs[i];
   }
+  const auto wall0 = std::chrono::steady_clock::now();
+  const unsigned long long k0 = g_kernels.load();
+  std::vector<OuterSolve> S(nprob);
   std::vector<int> rcs(nprob, 0);
   std::vector<std::string> errs(nprob);
-  std::vector<std::thread> th;
+  auto failed = [&](int i, int rc) {
+    if (rc < 0) {
+      rcs[i] = rc;
+      errs[i] = g_err;
+      S[i].done = true;
+    }
+    return rc < 0;
+  };
+  for (int i = 0; i < nprob; ++i) {
+    int rc = os_setup(hs[i], false, nrhs[i], q[i], u[i], opts, stats != nullptr, S[i]);
+    if (rc > 0) rc = fail(ELH_ERR_HIP, "launch failed");
+    if (failed(i, rc)) continue;
+    failed(i, os_begin(S[i]));
+  }
+  for (;;) {
+    std::vector<int> run;
+    for (int i = 0; i < nprob; ++i)
+      if (!S[i].done) run.push_back(i);
+    if (run.empty()) break;
+    for (int i : run) {
+      int rc = S[i].in_restart ? 0 : os_restart_begin(S[i]);
+      if (!rc) rc = os_iter_enqueue(S[i]);
+      if (rc > 0) rc = fail(ELH_ERR_HIP, "launch failed");
+      failed(i, rc);
+    }
+    for (int i : run)
+      if (!S[i].done) {
+        int rc = os_iter_finish(S[i]);
+        if (rc > 0) rc = fail(ELH_ERR_HIP, "launch failed");
+        failed(i, rc);
+      }
+  }
   for (int i = 0; i < nprob; ++i)
-    th.emplace_back([&, i]() {
-      rcs[i] = solve_impl(hs[i], false, nrhs[i], q[i], u[i], opts, stats ? stats + off[i] : nullptr);
-      if (rcs[i] < 0) errs[i] = g_err;  // thread-local message of the worker
-    });
-  for (auto& t : th) t.join();
+    if (!rcs[i]) {
+      int rc = os_finish(S[i]);
+      if (rc > 0) rc = fail(ELH_ERR_HIP, "copy failed");
+      failed(i, rc);
+    }
+  const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
   int worst = ELH_OK;
   for (int i = 0; i < nprob; ++i) {
-    if (rcs[i] < 0 && (worst >= 0 || rcs[i] < worst)) {
-      worst = rcs[i];
-      snprintf(g_err, sizeof(g_err), "problem %d: %s", i, errs[i].c_str());
-    } else if (rcs[i] > 0 && worst == ELH_OK) {
-      worst = rcs[i];
+    if (rcs[i] < 0) {
+      if (worst >= 0 || rcs[i] < worst) {
+        worst = rcs[i];
+        snprintf(g_err, sizeof(g_err), "problem %d: %s", i, errs[i].c_str());
+      }
+      continue;
     }
+    const int r = os_report(S[i], wall, g_kernels.load() - k0, stats ? stats + off[i] : nullptr);
+    if (r > 0 && worst == ELH_OK) worst = r;
   }
   return worst;
+}
+
+extern "C" int elh_solve_batch(int nprob, elh_handle* const* hs, const int* nrhs, const void* const* q,
+                               void* const* u, const elh_solve_opts* opts, elh_solve_stats* stats) {
+  return batch_drive(nprob, hs, nrhs, q, u, opts, stats);
+}
+
+// uneven-grid batch handle: problem handles on library-owned streams
+struct elh_batch {
+  std::vector<elh_handle*> h;
+  std::vector<hipStream_t> st;
+  std::vector<hipEvent_t> ev;
+  hipStream_t caller = nullptr;
+  hipEvent_t cev = nullptr;
+};
+
+extern "C" int elh_batch_destroy(elh_batch* B) {
+  if (!B) return 0;
+  for (auto* h : B->h) elh_destroy(h);
+  for (auto s : B->st) (void)hipStreamDestroy(s);
+  for (auto e : B->ev) (void)hipEventDestroy(e);
+  if (B->cev) (void)hipEventDestroy(B->cev);
+  delete B;
+  return 0;
+}
+
+extern "C" int elh_batch_create(int nprob, const elh_desc* descs, const double* const* lam, const double* const* mu,
+                                const double* const* rho, void* stream, elh_batch** out) {
+  if (!out) return fail(ELH_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (nprob < 1 || nprob > 4096 || !descs || !lam || !mu || !rho) return fail(ELH_ERR_ARG, "invalid batch arguments");
+  for (int i = 0; i < nprob; ++i) {
+    const int rc = check_desc(&descs[i]);
+    if (rc) return fail(rc, "problem %d: %s", i, std::string(g_err).c_str());
+  }
+  elh_batch* B = new elh_batch();
+  B->caller = (hipStream_t)stream;
+  if (hipEventCreateWithFlags(&B->cev, hipEventDisableTiming) != hipSuccess) {
+    elh_batch_destroy(B);
+    return fail(ELH_ERR_HIP, "event creation failed");
+  }
+  // the media were written on the caller's stream
+  if (hipEventRecord(B->cev, B->caller) != hipSuccess) {
+    elh_batch_destroy(B);
+    return fail(ELH_ERR_HIP, "event record failed");
+  }
+  for (int i = 0; i < nprob; ++i) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      if (s) (void)hipStreamDestroy(s);
+      elh_batch_destroy(B);
+      return fail(ELH_ERR_HIP, "stream creation failed");
+    }
+    B->st.push_back(s);
+    B->ev.push_back(e);
+    if (hipStreamWaitEvent(s, B->cev, 0) != hipSuccess) {
+      elh_batch_destroy(B);
+      return fail(ELH_ERR_HIP, "stream wait failed");
+    }
+    elh_handle* h = nullptr;
+    const int rc = elh_create(&descs[i], lam[i], mu[i], rho[i], s, &h);
+    if (rc) {
+      const std::string msg = g_err;
+      elh_batch_destroy(B);
+      return fail(rc, "problem %d: %s", i, msg.c_str());
+    }
+    B->h.push_back(h);
+  }
+  *out = B;
+  return 0;
+}
+
+extern "C" int elh_batch_size(const elh_batch* B) { return B ? (int)B->h.size() : ELH_ERR_ARG; }
+
+extern "C" int elh_batch_handle(elh_batch* B, int i, elh_handle** h) {
+  if (!B || !h || i < 0 || i >= (int)B->h.size()) return fail(ELH_ERR_ARG, "invalid batch or index");
+  *h = B->h[i];
+  return 0;
+}
+
+extern "C" int elh_batch_solve(elh_batch* B, const int* nrhs, const void* const* q, void* const* u,
+                               const elh_solve_opts* opts, elh_solve_stats* stats) {
+  if (!B) return fail(ELH_ERR_ARG, "batch is NULL");
+  const int n = (int)B->h.size();
+  // inputs were written on the caller's stream; outputs are ready on it
+  // when the call returns (after its own synchronisation)
+  HIPCHK(hipEventRecord(B->cev, B->caller));
+  for (int i = 0; i < n; ++i) HIPCHK(hipStreamWaitEvent(B->st[i], B->cev, 0));
+  const int rc = batch_drive(n, B->h.data(), nrhs, q, u, opts, stats);
+  for (int i = 0; i < n; ++i) {
+    if (hipEventRecord(B->ev[i], B->st[i]) != hipSuccess || hipStreamWaitEvent(B->caller, B->ev[i], 0) != hipSuccess)
+      return rc < 0 ? rc : fail(ELH_ERR_HIP, "stream join failed");
+  }
+  return rc;
 }
 
 extern "C" int elh_gradient(elh_handle* H, int nrhs, const void* u, const void* v, double* g_lam, double* g_mu,

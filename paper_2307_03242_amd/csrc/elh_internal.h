@@ -4,7 +4,18 @@
 #include <stdint.h>
 #include "elh_device.h"
 
+#include <atomic>
+
 namespace elh {
+
+// kernels this library has had executed: eager launches plus the kernel
+// nodes of replayed graphs (solve statistics, launches per iteration)
+extern std::atomic<unsigned long long> g_kernels;
+#define ELH_LAUNCH(...)                                                \
+  do {                                                                 \
+    ::elh::g_kernels.fetch_add(1, std::memory_order_relaxed);          \
+    hipLaunchKernelGGL(__VA_ARGS__);                                   \
+  } while (0)
 
 constexpr int MAXDOT = 16;         // most vectors in one fused multi-dot
 constexpr int MAXRHS_KRYLOV = 64;  // right-hand sides per Krylov solve (reduction buffers)
@@ -125,5 +136,16 @@ int launch_gm_hcol(int nrhs, int j, const double* dots, const double* part, int 
 int launch_gm_rotate(int nrhs, int j, const double* nrm2, const double* part, int nb, double* st, double* scale,
                      hipStream_t s);
 int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStream_t s);
+// Outer flexible GMRES bookkeeping on the device (per-rhs record of
+// GO_STRIDE doubles; stat: 4 doubles per rhs: live, jend, residual
+// estimate, non-finite flag).  par: 4 doubles per rhs: active, ||b||, rtol.
+constexpr int GO_STRIDE = GM_STRIDE + MAXDOT + 8;
+int launch_go_start(int nrhs, const double* nrm2, const double* part, int nb, const double* par, double* st,
+                    double* stat, hipStream_t s);
+int launch_go_hcol(int nrhs, int j, const double* dots, const double* part, int nb, double* st, double* coef,
+                   hipStream_t s);
+int launch_go_rotate(int nrhs, int j, const double* nrm2, const double* part, int nb, double* st, double* stat,
+                     hipStream_t s);
+int launch_go_update(int nrhs, int k, const double* st, double* coef, hipStream_t s);
 
 }  // namespace elh

@@ -283,7 +283,7 @@ template <typename T>
 int launch_kacz_sweep(const KaczArgs<T>& K, const void* b, const void* xin, void* scr, int nrhs, hipStream_t st) {
   const size_t lds = (size_t)K.ls * sizeof(cx<T>);
   if (lds > KACZ_MAX_LDS || K.ns > 128 || nrhs > 65535) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_kacz_sweep<T>, dim3(K.nreg, nrhs), dim3(64), lds, st, K, (const cx<T>*)b,
+  ELH_LAUNCH(k_kacz_sweep<T>, dim3(K.nreg, nrhs), dim3(64), lds, st, K, (const cx<T>*)b,
                      (const cx<T>*)xin, (cx<T>*)scr);
   return (int)hipGetLastError();
 }
@@ -291,14 +291,14 @@ int launch_kacz_sweep(const KaczArgs<T>& K, const void* b, const void* xin, void
 template <typename T>
 int launch_kacz_avg(const KaczArgs<T>& K, const void* scr, void* x, int nrhs, hipStream_t st) {
   const int64_t n = (int64_t)K.dim * K.fs * nrhs;
-  hipLaunchKernelGGL(k_kacz_avg<T>, dim3(ngrid(n, 256)), dim3(256), 0, st, K, (const cx<T>*)scr, (cx<T>*)x, nrhs);
+  ELH_LAUNCH(k_kacz_avg<T>, dim3(ngrid(n, 256)), dim3(256), 0, st, K, (const cx<T>*)scr, (cx<T>*)x, nrhs);
   return (int)hipGetLastError();
 }
 
 template <typename T>
 int launch_kacz_spmv(const KaczArgs<T>& K, const void* x, const void* b, void* y, int nrhs, hipStream_t st) {
   const int64_t waves = K.vs * nrhs;
-  hipLaunchKernelGGL(k_kacz_spmv<T>, dim3(ngrid(waves, 4)), dim3(256), 0, st, K, (const cx<T>*)x,
+  ELH_LAUNCH(k_kacz_spmv<T>, dim3(ngrid(waves, 4)), dim3(256), 0, st, K, (const cx<T>*)x,
                      (const cx<T>*)b, (cx<T>*)y, nrhs);
   return (int)hipGetLastError();
 }
@@ -306,7 +306,7 @@ int launch_kacz_spmv(const KaczArgs<T>& K, const void* x, const void* b, void* y
 template <typename T>
 int launch_kacz_elem(int mode, int dim, int64_t fs, int64_t vs, int nrhs, const void* app, int cj, const void* b,
                      const void* y, void* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_kacz_elem<T>, dim3(ngrid(vs * nrhs, 256)), dim3(256), 0, st, mode, dim, fs, vs, nrhs,
+  ELH_LAUNCH(k_kacz_elem<T>, dim3(ngrid(vs * nrhs, 256)), dim3(256), 0, st, mode, dim, fs, vs, nrhs,
                      (const cx<T>*)app, cj, (const cx<T>*)b, (const cx<T>*)y, (cx<T>*)out);
   return (int)hipGetLastError();
 }

@@ -47,11 +47,11 @@ int launch_apply(const LevelArgs<T>& L, int dim, bool adj, const void* x, const 
   const cx<T>* bp = (const cx<T>*)b;
   cx<T>* yp = (cx<T>*)y;
   if (dim == 3) {
-    if (adj) hipLaunchKernelGGL((k_apply<3, true, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
-    else hipLaunchKernelGGL((k_apply<3, false, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
+    if (adj) ELH_LAUNCH((k_apply<3, true, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
+    else ELH_LAUNCH((k_apply<3, false, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
   } else {
-    if (adj) hipLaunchKernelGGL((k_apply<2, true, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
-    else hipLaunchKernelGGL((k_apply<2, false, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
+    if (adj) ELH_LAUNCH((k_apply<2, true, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
+    else ELH_LAUNCH((k_apply<2, false, T>), grd, blk, 0, st, L, xp, bp, yp, nrhs);
   }
   return (int)hipGetLastError();
 }
@@ -381,13 +381,13 @@ int launch_vanka(const LevelArgs<T>& L, int dim, bool adj, const void* r, void* 
   cx<T>* xp = (cx<T>*)x;
   if (dim == 3) {
     if (work > 0x7fffffffll || L.fs > 0x7fffffffll) return (int)hipErrorInvalidValue;
-    if (adj && write) hipLaunchKernelGGL((k_vanka3<true, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
-    else if (adj) hipLaunchKernelGGL((k_vanka3<true, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
-    else if (write) hipLaunchKernelGGL((k_vanka3<false, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
-    else hipLaunchKernelGGL((k_vanka3<false, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    if (adj && write) ELH_LAUNCH((k_vanka3<true, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else if (adj) ELH_LAUNCH((k_vanka3<true, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else if (write) ELH_LAUNCH((k_vanka3<false, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else ELH_LAUNCH((k_vanka3<false, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
   } else {
-    if (adj) hipLaunchKernelGGL((k_vanka<2, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
-    else hipLaunchKernelGGL((k_vanka<2, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    if (adj) ELH_LAUNCH((k_vanka<2, true, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
+    else ELH_LAUNCH((k_vanka<2, false, T>), grd, blk, 0, st, L, rp, xp, colour, (T)w, nrhs);
   }
   return (int)hipGetLastError();
 }
@@ -649,9 +649,9 @@ int launch_restrict(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const
                     hipStream_t st) {
   dim3 blk(256), grd((unsigned)((C.fs + 255) / 256), nrhs);
   if (dim == 3)
-    hipLaunchKernelGGL((k_restrict<3, T>), grd, blk, 0, st, F, C, (const cx<T>*)r, (cx<T>*)rc, nrhs);
+    ELH_LAUNCH((k_restrict<3, T>), grd, blk, 0, st, F, C, (const cx<T>*)r, (cx<T>*)rc, nrhs);
   else
-    hipLaunchKernelGGL((k_restrict<2, T>), grd, blk, 0, st, F, C, (const cx<T>*)r, (cx<T>*)rc, nrhs);
+    ELH_LAUNCH((k_restrict<2, T>), grd, blk, 0, st, F, C, (const cx<T>*)r, (cx<T>*)rc, nrhs);
   return (int)hipGetLastError();
 }
 template <typename T>
@@ -663,11 +663,11 @@ int launch_restrict_resid(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim,
   const cx<T>* bp = (const cx<T>*)b;
   cx<T>* op = (cx<T>*)rc;
   if (dim == 3) {
-    if (adj) hipLaunchKernelGGL((k_restrict_resid<3, true, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
-    else hipLaunchKernelGGL((k_restrict_resid<3, false, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
+    if (adj) ELH_LAUNCH((k_restrict_resid<3, true, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
+    else ELH_LAUNCH((k_restrict_resid<3, false, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
   } else {
-    if (adj) hipLaunchKernelGGL((k_restrict_resid<2, true, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
-    else hipLaunchKernelGGL((k_restrict_resid<2, false, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
+    if (adj) ELH_LAUNCH((k_restrict_resid<2, true, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
+    else ELH_LAUNCH((k_restrict_resid<2, false, T>), grd, blk, 0, st, F, C, xp, bp, op, nrhs);
   }
   return (int)hipGetLastError();
 }
@@ -681,12 +681,12 @@ int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, co
                        hipStream_t st) {
   dim3 blk(256), grd((unsigned)((F.fs + 255) / 256), nrhs);
   if (dim == 3 && F.fs <= 0x7fffffffll && (F.n[0] & 1) == 0 && F.n[0] == 2 * C.n[0])
-    hipLaunchKernelGGL((k_prolong3<T>), dim3((unsigned)((F.fs / 2 + 255) / 256), nrhs), blk, 0, st, F, C,
+    ELH_LAUNCH((k_prolong3<T>), dim3((unsigned)((F.fs / 2 + 255) / 256), nrhs), blk, 0, st, F, C,
                        (const cx<T>*)e, (cx<T>*)x, nrhs);
   else if (dim == 3)
-    hipLaunchKernelGGL((k_prolong_add<3, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
+    ELH_LAUNCH((k_prolong_add<3, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
   else
-    hipLaunchKernelGGL((k_prolong_add<2, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
+    ELH_LAUNCH((k_prolong_add<2, T>), grd, blk, 0, st, F, C, (const cx<T>*)e, (cx<T>*)x, nrhs);
   return (int)hipGetLastError();
 }
 template int launch_restrict<double>(const LevelArgs<double>&, const LevelArgs<double>&, int, const void*, void*,
@@ -795,9 +795,9 @@ int launch_gradient(const LevelArgs<double>& L, int dim, int nrhs, const void* u
                     double* gm, double* gr, hipStream_t st) {
   dim3 blk(256), grd((unsigned)((L.fs + 255) / 256));
   if (dim == 3)
-    hipLaunchKernelGGL(k_gradient<3>, grd, blk, 0, st, L, nrhs, (const cx<double>*)u, (const cx<double>*)v, gl, gm, gr);
+    ELH_LAUNCH(k_gradient<3>, grd, blk, 0, st, L, nrhs, (const cx<double>*)u, (const cx<double>*)v, gl, gm, gr);
   else
-    hipLaunchKernelGGL(k_gradient<2>, grd, blk, 0, st, L, nrhs, (const cx<double>*)u, (const cx<double>*)v, gl, gm, gr);
+    ELH_LAUNCH(k_gradient<2>, grd, blk, 0, st, L, nrhs, (const cx<double>*)u, (const cx<double>*)v, gl, gm, gr);
   return (int)hipGetLastError();
 }
 
@@ -836,13 +836,13 @@ __global__ void k_media_finish(int64_t n, const double* __restrict__ lam, const 
 
 int launch_coarsen_media(int dim, const int* nf, const double* a, double* out, hipStream_t st) {
   int64_t n = (int64_t)(nf[0] / 2) * (nf[1] / 2) * (dim == 3 ? nf[2] / 2 : 1);
-  hipLaunchKernelGGL(k_coarsen_media, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dim, nf[0], nf[1],
+  ELH_LAUNCH(k_coarsen_media, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dim, nf[0], nf[1],
                      nf[2], a, out);
   return (int)hipGetLastError();
 }
 int launch_media_finish(int64_t n, const double* lam, const double* mu, const double* rho, double* kap, float* mu32,
                         float* rho32, float* kap32, hipStream_t st) {
-  hipLaunchKernelGGL(k_media_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lam, mu, rho, kap,
+  ELH_LAUNCH(k_media_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lam, mu, rho, kap,
                      mu32, rho32, kap32);
   return (int)hipGetLastError();
 }
@@ -974,15 +974,15 @@ int launch_multidot(int m, const void* V, int64_t vstride_vec, int64_t vstride_r
   const TV* Vp = (const TV*)V;
   const TW* wp = (const TW*)w;
   switch (m) {
-    case 1: hipLaunchKernelGGL((k_multidot<TV, TW, 1>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
-    case 2: hipLaunchKernelGGL((k_multidot<TV, TW, 2>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
-    case 3: hipLaunchKernelGGL((k_multidot<TV, TW, 3>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
-    case 4: hipLaunchKernelGGL((k_multidot<TV, TW, 4>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
-    case 5: hipLaunchKernelGGL((k_multidot<TV, TW, 5>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
-    case 6: hipLaunchKernelGGL((k_multidot<TV, TW, 6>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
-    default: hipLaunchKernelGGL((k_multidot<TV, TW, 0>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part);
+    case 1: ELH_LAUNCH((k_multidot<TV, TW, 1>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 2: ELH_LAUNCH((k_multidot<TV, TW, 2>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 3: ELH_LAUNCH((k_multidot<TV, TW, 3>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 4: ELH_LAUNCH((k_multidot<TV, TW, 4>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 5: ELH_LAUNCH((k_multidot<TV, TW, 5>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    case 6: ELH_LAUNCH((k_multidot<TV, TW, 6>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part); break;
+    default: ELH_LAUNCH((k_multidot<TV, TW, 0>), grd, blk, 0, st, m, Vp, vstride_vec, vstride_rhs, wp, wstride_rhs, len, part);
   }
-  if (out) hipLaunchKernelGGL(k_reduce_parts, dim3(2 * m, nrhs), dim3(256), 0, st, 2 * m, nb, part, out);
+  if (out) ELH_LAUNCH(k_reduce_parts, dim3(2 * m, nrhs), dim3(256), 0, st, 2 * m, nb, part, out);
   return (int)hipGetLastError();
 }
 template int launch_multidot<cx<double>, cx<double>>(int, const void*, int64_t, int64_t, const void*, int64_t,
@@ -1019,10 +1019,10 @@ int launch_multiaxpy(int m, const double* coef, const void* V, int64_t vstride_v
                      int64_t wstride_rhs, int64_t len, int nrhs, hipStream_t st, bool set) {
   const dim3 grd((unsigned)((len + 255) / 256), nrhs), blk(256);
   if (set)
-    hipLaunchKernelGGL((k_multiaxpy<TV, TW, true>), grd, blk, 0, st, m, coef, (const TV*)V, vstride_vec, vstride_rhs,
+    ELH_LAUNCH((k_multiaxpy<TV, TW, true>), grd, blk, 0, st, m, coef, (const TV*)V, vstride_vec, vstride_rhs,
                        (TW*)w, wstride_rhs, len);
   else
-    hipLaunchKernelGGL((k_multiaxpy<TV, TW, false>), grd, blk, 0, st, m, coef, (const TV*)V, vstride_vec,
+    ELH_LAUNCH((k_multiaxpy<TV, TW, false>), grd, blk, 0, st, m, coef, (const TV*)V, vstride_vec,
                        vstride_rhs, (TW*)w, wstride_rhs, len);
   return (int)hipGetLastError();
 }
@@ -1101,14 +1101,14 @@ int launch_axpy_norm(int m, const double* coef, const void* V, int64_t vstride_v
   const dim3 grd(nb, nrhs), blk(RED_THREADS);
   const TV* Vp = (const TV*)V;
   switch (m) {
-    case 1: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 1>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
-    case 2: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 2>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
-    case 3: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 3>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
-    case 4: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 4>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
-    case 5: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 5>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
-    default: hipLaunchKernelGGL((k_axpy_norm<TV, TF, 0>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part);
+    case 1: ELH_LAUNCH((k_axpy_norm<TV, TF, 1>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    case 2: ELH_LAUNCH((k_axpy_norm<TV, TF, 2>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    case 3: ELH_LAUNCH((k_axpy_norm<TV, TF, 3>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    case 4: ELH_LAUNCH((k_axpy_norm<TV, TF, 4>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    case 5: ELH_LAUNCH((k_axpy_norm<TV, TF, 5>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part); break;
+    default: ELH_LAUNCH((k_axpy_norm<TV, TF, 0>), grd, blk, 0, st, m, coef, Vp, vstride_vec, vstride_rhs, (TV*)w, wstride_rhs, (TF*)f, fstride_rhs, len, part);
   }
-  if (out) hipLaunchKernelGGL(k_reduce_parts, dim3(2, nrhs), dim3(256), 0, st, 2, nb, part, out);
+  if (out) ELH_LAUNCH(k_reduce_parts, dim3(2, nrhs), dim3(256), 0, st, 2, nb, part, out);
   return (int)hipGetLastError();
 }
 template int launch_axpy_norm<cx<double>, cx<float>>(int, const double*, const void*, int64_t, int64_t, void*,
@@ -1169,7 +1169,7 @@ int launch_kcycle_coef(int stage, const double* dots, const double* part, int nb
                        int nrhs, hipStream_t st) {
   if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * (stage == 1 ? 4 : 6) > FUSE_VALS))
     return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_kcycle_coef, dim3(1), dim3(256), 0, st, stage, dots, part, nb, coef, state, nrhs);
+  ELH_LAUNCH(k_kcycle_coef, dim3(1), dim3(256), 0, st, stage, dots, part, nb, coef, state, nrhs);
   return (int)hipGetLastError();
 }
 
@@ -1193,7 +1193,7 @@ __global__ void __launch_bounds__(256) k_scale_copy(const double* __restrict__ a
 template <typename TX, typename TY>
 int launch_scale_copy(const double* a, const void* x, int64_t xstride, void* y, int64_t ystride, int64_t len,
                       int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL((k_scale_copy<TX, TY>), dim3((unsigned)((len + 255) / 256), nrhs), dim3(256), 0, st, a,
+  ELH_LAUNCH((k_scale_copy<TX, TY>), dim3((unsigned)((len + 255) / 256), nrhs), dim3(256), 0, st, a,
                      (const TX*)x, xstride, (TY*)y, ystride, len);
   return (int)hipGetLastError();
 }
@@ -1332,23 +1332,207 @@ __global__ void k_gm_backsolve(int nrhs, int k, const double* __restrict__ st, d
 int launch_gm_start(int nrhs, const double* nrm2, const double* part, int nb, double* st, double* scale,
                     hipStream_t s) {
   if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 > FUSE_VALS)) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gm_start, dim3(1), dim3(256), 0, s, nrhs, nrm2, part, nb, st, scale);
+  ELH_LAUNCH(k_gm_start, dim3(1), dim3(256), 0, s, nrhs, nrm2, part, nb, st, scale);
   return (int)hipGetLastError();
 }
 int launch_gm_hcol(int nrhs, int j, const double* dots, const double* part, int nb, double* st, double* coef,
                    hipStream_t s) {
   if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 * (j + 1) > FUSE_VALS)) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gm_hcol, dim3(1), dim3(256), 0, s, nrhs, j, dots, part, nb, st, coef);
+  ELH_LAUNCH(k_gm_hcol, dim3(1), dim3(256), 0, s, nrhs, j, dots, part, nb, st, coef);
   return (int)hipGetLastError();
 }
 int launch_gm_rotate(int nrhs, int j, const double* nrm2, const double* part, int nb, double* st, double* scale,
                      hipStream_t s) {
   if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 > FUSE_VALS)) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gm_rotate, dim3(1), dim3(256), 0, s, nrhs, j, nrm2, part, nb, st, scale);
+  ELH_LAUNCH(k_gm_rotate, dim3(1), dim3(256), 0, s, nrhs, j, nrm2, part, nb, st, scale);
   return (int)hipGetLastError();
 }
 int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_backsolve, dim3(1), dim3(64), 0, s, nrhs, k, st, coef);
+  ELH_LAUNCH(k_gm_backsolve, dim3(1), dim3(64), 0, s, nrhs, k, st, coef);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Outer flexible GMRES with its bookkeeping on the device, one thread per
+// right-hand side.  The basis stays unnormalised as in the host driver:
+// V_i = v_i / sig_i, h_ij = sig_i sig_j <V_i, A Z_j>, h_{j+1,j} = sig_j
+// ||V_{j+1}||, x += sum_j (y_j sig_j) Z_j.  Per rhs: the GM_STRIDE block
+// (H, g, sines, cosines) followed by sig_0..sig_MAXDOT and the scalars
+// below (GO_STRIDE doubles).  stat (4 doubles per rhs, copied to the host
+// after every step): live, jend, residual estimate |g_{j+1}| / ||b||, bad.
+// ---------------------------------------------------------------------------
+constexpr int GO_SIG = GM_STRIDE, GO_NB = GO_SIG + MAXDOT + 1, GO_RTOL = GO_NB + 1, GO_LIVE = GO_NB + 2,
+              GO_JEND = GO_NB + 3;
+static_assert(GO_JEND < GO_STRIDE, "outer GMRES record");
+
+__device__ inline double* go_rec(double* st, int s) { return st + (size_t)s * GO_STRIDE; }
+
+// restart: g = (beta, 0, ...), sig_0 = 1/beta; par[4s..]: active, ||b||, rtol
+__global__ void __launch_bounds__(256) k_go_start(int nrhs, const double* __restrict__ nrm2_in,
+                                                   const double* __restrict__ part, int nb,
+                                                   const double* __restrict__ par, double* __restrict__ st,
+                                                   double* __restrict__ stat) {
+  __shared__ double vals[FUSE_VALS];
+  const double* __restrict__ nrm2 = small_reduction(nrhs * 2, 2, nrm2_in, part, nb, vals);
+  const int s = threadIdx.x;
+  if (s >= nrhs) return;
+  double* r = go_rec(st, s);
+  const double beta = sqrt(nrm2[2 * s]);
+  const bool act = par[4 * s] != 0.0 && beta > 0;
+  zc* g = gm_g(r, 0);
+  for (int i = 0; i < MAXDOT; ++i) g[i] = {0.0, 0.0};
+  g[0] = {beta, 0.0};
+  r[GO_SIG] = act ? 1.0 / beta : 0.0;
+  r[GO_NB] = par[4 * s + 1];
+  r[GO_RTOL] = par[4 * s + 2];
+  r[GO_LIVE] = act ? 1.0 : 0.0;
+  r[GO_JEND] = -1.0;
+  stat[4 * s] = r[GO_LIVE];
+  stat[4 * s + 1] = -1.0;
+  stat[4 * s + 2] = r[GO_NB] > 0 ? beta / r[GO_NB] : 0.0;
+  stat[4 * s + 3] = isfinite(beta) ? 0.0 : 1.0;
+}
+
+// after the dots d_i = <V_i, A Z_j>: column j of H (live rhs) and the
+// Gram-Schmidt coefficients -sig_i^2 d_i (every rhs)
+__global__ void __launch_bounds__(256) k_go_hcol(int nrhs, int j, const double* __restrict__ dots_in,
+                                                  const double* __restrict__ part, int nb, double* __restrict__ st,
+                                                  double* __restrict__ coef) {
+  __shared__ double vals[FUSE_VALS];
+  const double* __restrict__ dots = small_reduction(nrhs * 2 * (j + 1), 2 * (j + 1), dots_in, part, nb, vals);
+  const int s = threadIdx.x;
+  if (s >= nrhs) return;
+  double* r = go_rec(st, s);
+  const bool live = r[GO_LIVE] != 0.0;
+  const double sj = r[GO_SIG + j];
+  for (int i = 0; i <= j; ++i) {
+    const double dr = dots[(s * (j + 1) + i) * 2], di = dots[(s * (j + 1) + i) * 2 + 1];
+    const double si = r[GO_SIG + i];
+    if (live) *gm_H(r, 0, i, j) = {(si * sj) * dr, (si * sj) * di};
+    coef[(s * (j + 1) + i) * 2] = -(si * si) * dr;
+    coef[(s * (j + 1) + i) * 2 + 1] = -(si * si) * di;
+  }
+}
+
+// after ||V_{j+1}||^2: sig_{j+1}; for live rhs the subdiagonal, the previous
+// rotations, the new rotation, g, the residual estimate and the stop test
+__global__ void __launch_bounds__(256) k_go_rotate(int nrhs, int j, const double* __restrict__ nrm2_in,
+                                                    const double* __restrict__ part, int nb, double* __restrict__ st,
+                                                    double* __restrict__ stat) {
+  __shared__ double vals[FUSE_VALS];
+  const double* __restrict__ nrm2 = small_reduction(nrhs * 2, 2, nrm2_in, part, nb, vals);
+  const int s = threadIdx.x;
+  if (s >= nrhs) return;
+  double* r = go_rec(st, s);
+  const double wn = sqrt(nrm2[2 * s]);
+  const double sj = r[GO_SIG + j];
+  r[GO_SIG + j + 1] = wn > 0 ? 1.0 / wn : 0.0;
+  if (r[GO_LIVE] == 0.0) {
+    stat[4 * s] = 0.0;
+    return;
+  }
+  const double hn = sj * wn;
+  if (!isfinite(hn)) {
+    r[GO_LIVE] = 0.0;
+    stat[4 * s] = 0.0;
+    stat[4 * s + 3] = 1.0;
+    return;
+  }
+  *gm_H(r, 0, j + 1, j) = {hn, 0.0};
+  zc* sn = gm_sn(r, 0);
+  double* cs = gm_cs(r, 0);
+  for (int i = 0; i < j; ++i) {
+    zc a = *gm_H(r, 0, i, j), b = *gm_H(r, 0, i + 1, j);
+    zc t = zmul(sn[i], b);
+    zc na = {cs[i] * a.re + t.re, cs[i] * a.im + t.im};
+    zc u = zmul(zconj(sn[i]), a);
+    zc nbv = {-u.re + cs[i] * b.re, -u.im + cs[i] * b.im};
+    *gm_H(r, 0, i, j) = na;
+    *gm_H(r, 0, i + 1, j) = nbv;
+  }
+  zc a = *gm_H(r, 0, j, j), b = *gm_H(r, 0, j + 1, j);
+  double c;
+  zc sg;
+  const double aa = zabs(a), bb = zabs(b);
+  if (bb == 0) { c = 1; sg = {0, 0}; }
+  else if (aa == 0) { c = 0; sg = {b.re / bb, -b.im / bb}; }
+  else {
+    const double den = hypot(aa, bb);
+    c = aa / den;
+    const zc ph = {a.re / aa, a.im / aa};
+    sg = zmul(ph, zc{b.re / den, -b.im / den});
+  }
+  cs[j] = c;
+  sn[j] = sg;
+  const zc t = zmul(sg, b);
+  *gm_H(r, 0, j, j) = {c * a.re + t.re, c * a.im + t.im};
+  *gm_H(r, 0, j + 1, j) = {0, 0};
+  zc* g = gm_g(r, 0);
+  const zc gj = g[j];
+  const zc u = zmul(zconj(sg), gj);
+  g[j + 1] = {-u.re, -u.im};
+  g[j] = {c * gj.re, c * gj.im};
+  r[GO_JEND] = j;
+  const double res = zabs(g[j + 1]) / r[GO_NB];
+  const bool stop = res <= r[GO_RTOL] || hn == 0;
+  if (stop) r[GO_LIVE] = 0.0;
+  stat[4 * s] = stop ? 0.0 : 1.0;
+  stat[4 * s + 1] = j;
+  stat[4 * s + 2] = res;
+  stat[4 * s + 3] = 0.0;
+}
+
+// end of a restart: y = R^{-1} g over the jend+1 columns of each rhs, and
+// the update coefficients y_i sig_i (zero beyond jend, all zero for a rhs
+// that took no step), k per rhs in coef
+__global__ void k_go_update(int nrhs, int k, const double* __restrict__ st, double* __restrict__ coef) {
+  const int s = threadIdx.x;
+  if (s >= nrhs) return;
+  double* r = const_cast<double*>(st) + (size_t)s * GO_STRIDE;
+  const int kk = (int)r[GO_JEND] + 1;
+  const zc* g = gm_g(r, 0);
+  zc y[MAXDOT];
+  for (int i = kk - 1; i >= 0; --i) {
+    zc acc = g[i];
+    for (int q = i + 1; q < kk; ++q) {
+      const zc t = zmul(*gm_H(r, 0, i, q), y[q]);
+      acc.re -= t.re;
+      acc.im -= t.im;
+    }
+    const zc d = *gm_H(r, 0, i, i);
+    const double dd = d.re * d.re + d.im * d.im;
+    y[i] = dd > 0 ? zc{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd} : zc{0, 0};
+  }
+  for (int i = 0; i < k; ++i) {
+    const double sg = i < kk ? r[GO_SIG + i] : 0.0;
+    coef[(s * k + i) * 2] = i < kk ? y[i].re * sg : 0.0;
+    coef[(s * k + i) * 2 + 1] = i < kk ? y[i].im * sg : 0.0;
+  }
+}
+
+int launch_go_start(int nrhs, const double* nrm2, const double* part, int nb, const double* par, double* st,
+                    double* stat, hipStream_t s) {
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 > FUSE_VALS)) return (int)hipErrorInvalidValue;
+  ELH_LAUNCH(k_go_start, dim3(1), dim3(256), 0, s, nrhs, nrm2, part, nb, par, st, stat);
+  return (int)hipGetLastError();
+}
+int launch_go_hcol(int nrhs, int j, const double* dots, const double* part, int nb, double* st, double* coef,
+                   hipStream_t s) {
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || j + 1 >= MAXDOT || (part && nrhs * 2 * (j + 1) > FUSE_VALS))
+    return (int)hipErrorInvalidValue;
+  ELH_LAUNCH(k_go_hcol, dim3(1), dim3(256), 0, s, nrhs, j, dots, part, nb, st, coef);
+  return (int)hipGetLastError();
+}
+int launch_go_rotate(int nrhs, int j, const double* nrm2, const double* part, int nb, double* st, double* stat,
+                     hipStream_t s) {
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || j + 1 >= MAXDOT || (part && nrhs * 2 > FUSE_VALS))
+    return (int)hipErrorInvalidValue;
+  ELH_LAUNCH(k_go_rotate, dim3(1), dim3(256), 0, s, nrhs, j, nrm2, part, nb, st, stat);
+  return (int)hipGetLastError();
+}
+int launch_go_update(int nrhs, int k, const double* st, double* coef, hipStream_t s) {
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || k < 1 || k >= MAXDOT) return (int)hipErrorInvalidValue;
+  ELH_LAUNCH(k_go_update, dim3(1), dim3(64), 0, s, nrhs, k, st, coef);
   return (int)hipGetLastError();
 }
 
@@ -1439,11 +1623,11 @@ __global__ void k_gj_eliminate(int64_t N, int64_t k, const cx<double>* __restric
 }
 
 int launch_dense_assemble_prep(int64_t N, void* E, hipStream_t st) {
-  hipLaunchKernelGGL(k_unit_vectors, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, N, (cx<double>*)E);
+  ELH_LAUNCH(k_unit_vectors, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, N, (cx<double>*)E);
   return (int)hipGetLastError();
 }
 int launch_dense_fix(int64_t N, const int* isb, void* A, hipStream_t st) {
-  hipLaunchKernelGGL(k_fix_boundary_rows, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, isb,
+  ELH_LAUNCH(k_fix_boundary_rows, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, isb,
                      (cx<double>*)A);
   return (int)hipGetLastError();
 }
@@ -1452,17 +1636,17 @@ int launch_dense_invert(int64_t N, void* A, void* B, void* col, int* piv, hipStr
   cx<double>* a = (cx<double>*)A;
   cx<double>* b = (cx<double>*)B;
   cx<double>* c = (cx<double>*)col;
-  hipLaunchKernelGGL(k_unit_vectors, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, N, b);
+  ELH_LAUNCH(k_unit_vectors, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, N, b);
   for (int64_t k = 0; k < N; ++k) {
     // col has N+1 entries: col[N] carries the pivot value
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, st, N, k, (const cx<double>*)a, piv, c + N);
-    hipLaunchKernelGGL(k_gj_swap_scale, dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, st, N, k,
+    ELH_LAUNCH(k_gj_pivot, dim3(1), dim3(256), 0, st, N, k, (const cx<double>*)a, piv, c + N);
+    ELH_LAUNCH(k_gj_swap_scale, dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, st, N, k,
                        (const int*)piv, a, b, (const cx<double>*)(c + N));
-    hipLaunchKernelGGL(k_gj_column, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, k,
+    ELH_LAUNCH(k_gj_column, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, k,
                        (const cx<double>*)a, c);
     unsigned gx = (unsigned)((2 * N + 255) / 256);
     if (gx > 16) gx = 16;
-    hipLaunchKernelGGL(k_gj_eliminate, dim3(gx, (unsigned)N), dim3(256), 0, st, N, k, (const cx<double>*)c, a, b);
+    ELH_LAUNCH(k_gj_eliminate, dim3(gx, (unsigned)N), dim3(256), 0, st, N, k, (const cx<double>*)c, a, b);
   }
   return (int)hipGetLastError();
 }
@@ -1507,10 +1691,10 @@ template <typename T>
 int launch_dense_mv(int64_t N, const void* Q, int transposed, int cj, const void* b, void* x, int nrhs,
                     hipStream_t st) {
   if (transposed)
-    hipLaunchKernelGGL((k_dense_mv<T>), dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, N,
+    ELH_LAUNCH((k_dense_mv<T>), dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, N,
                        (const cx<T>*)Q, 1, cj, (const cx<T>*)b, (cx<T>*)x, nrhs);
   else
-    hipLaunchKernelGGL((k_dense_mv<T>), dim3((unsigned)((N + 3) / 4), nrhs), dim3(256), 0, st, N, (const cx<T>*)Q,
+    ELH_LAUNCH((k_dense_mv<T>), dim3((unsigned)((N + 3) / 4), nrhs), dim3(256), 0, st, N, (const cx<T>*)Q,
                        0, cj, (const cx<T>*)b, (cx<T>*)x, nrhs);
   return (int)hipGetLastError();
 }
@@ -1527,7 +1711,7 @@ int launch_zero(void* p, int64_t bytes, hipStream_t st) {
   if (n8 == 0) return 0;
   int64_t nb = (n8 + 255) / 256;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, st, (uint2*)p, n8);
+  ELH_LAUNCH(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, st, (uint2*)p, n8);
   return (int)hipGetLastError();
 }
 

@@ -873,10 +873,10 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
   const int per_xcd = (ntiles + 7) / 8;
   dim3 blk(WV_LANES, 3), grd(8 * per_xcd);
   if (b)
-    hipLaunchKernelGGL((k_apply3d_w3<T, TI, true>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)b,
+    ELH_LAUNCH((k_apply3d_w3<T, TI, true>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)b,
                        (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
   else
-    hipLaunchKernelGGL((k_apply3d_w3<T, TI, false>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)nullptr,
+    ELH_LAUNCH((k_apply3d_w3<T, TI, false>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)nullptr,
                        (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
   return (int)hipGetLastError();
 }
@@ -894,10 +894,10 @@ int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, v
   const int per_xcd = (ntiles + 7) / 8;
   dim3 blk(WV_LANES, 3), grd(8 * per_xcd);
   if (b)
-    hipLaunchKernelGGL((k_apply3d_w3_adj<T, true>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b,
+    ELH_LAUNCH((k_apply3d_w3_adj<T, true>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b,
                        (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
   else
-    hipLaunchKernelGGL((k_apply3d_w3_adj<T, false>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)nullptr,
+    ELH_LAUNCH((k_apply3d_w3_adj<T, false>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)nullptr,
                        (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
   return (int)hipGetLastError();
 }
@@ -919,10 +919,10 @@ int launch_restrict_resid3d_w3(const LevelArgs<T>& F, const LevelArgs<T>& Cl, bo
   const int per_xcd = (ntiles + 7) / 8;
   dim3 blk(WV_LANES, 7), grd(8 * per_xcd);
   if (adj)
-    hipLaunchKernelGGL((k_restrict_resid3d_w3<T, true>), grd, blk, 0, st, F, Cl, (const cx<T>*)x, (const cx<T>*)b,
+    ELH_LAUNCH((k_restrict_resid3d_w3<T, true>), grd, blk, 0, st, F, Cl, (const cx<T>*)x, (const cx<T>*)b,
                        (cx<T>*)rc, tiles_x, nzc, zc, ntiles, per_xcd);
   else
-    hipLaunchKernelGGL((k_restrict_resid3d_w3<T, false>), grd, blk, 0, st, F, Cl, (const cx<T>*)x,
+    ELH_LAUNCH((k_restrict_resid3d_w3<T, false>), grd, blk, 0, st, F, Cl, (const cx<T>*)x,
                        (const cx<T>*)b, (cx<T>*)rc, tiles_x, nzc, zc, ntiles, per_xcd);
   return (int)hipGetLastError();
 }
