@@ -241,19 +241,23 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
   T nmu[3], nrho[4], nrhoL;
   T na3;  // x_3 part of gamma~ for plane z-1: a table entry fetched with the plane-z loads, as a
           // vector load, so no wait on the scalar cache stalls the LDS hand-off
-  // float64: b of this wavefront's row and, for the p row (wavefront 0),
-  // kappa and b_p of plane z-1 are fetched with the plane-z loads, so the
-  // stores at the end of a step wait for nothing issued during it (12-14 %
-  // faster at two waves per SIMD).  float32 loads them in the step itself:
-  // as fast at four waves per SIMD, and 7-20 % less HBM traffic.
+  // kappa and b_p of plane z-1 for the p row (wavefront 0) are fetched with
+  // the plane-z loads: loaded after the barrier in the step itself, waiting
+  // for them would also wait for the whole next-plane prefetch (vector loads
+  // complete in order), once per plane, and the barrier makes the other two
+  // wavefronts wait with it.  float64 also fetches the b of this wavefront's
+  // row a plane ahead (12-14 % faster at two waves per SIMD); float32 loads
+  // it at the start of the step, before the prefetch, where it delays
+  // nothing (fetched a plane ahead it gave no time and 7-20 % more traffic).
   constexpr bool PF = sizeof(T) == 8;
+  constexpr bool PFP = true;
   T nkq = T(0);
   cx<T> nbp = czero<T>(), nbq = czero<T>();
   const __amdgpu_buffer_rsrc_t RABL = rsrc(C.ablz, C.has_abl ? 2 * n3 * RBY : 0);
   auto load_next = [&](int z) {
     na3 = bload<T>(RABL, 0, ((K == 2 ? n3 : 0) + min(max(z - 1, 0), n3 - 1)) * RBY);
     if (PF && RESID) nbq = bload<cx<T>>(C.RB[K], vu[1], zcl(z - 1) * CB);
-    if (PF && K == 0) {
+    if (PFP && K == 0) {
       nkq = bload<T>(C.RKAP, vr[2], zcl(z - 1) * RBY);
       if (RESID) nbp = bload<cx<T>>(C.RB[3], vu[1], zcl(z - 1) * CB);
     }
@@ -426,9 +430,9 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
     lds_barrier_w3();
     if (K == 0 && (emit || (RR && C.role != 2))) {
       cx<T> vp = C.ih * dv + DV[t & 1][1][lane] + DV[t & 1][2][lane];
-      const T kq = PF ? kqp : bload<T>(C.RKAP, vr[2], zcl(t) * RBY);
+      const T kq = PFP ? kqp : bload<T>(C.RKAP, vr[2], zcl(t) * RBY);
       vp += kq * PC;
-      if (RESID) vp = (PF ? bpp : bload<cx<T>>(C.RB[3], vu[1], sc)) - vp;
+      if (RESID) vp = (PFP ? bpp : bload<cx<T>>(C.RB[3], vu[1], sc)) - vp;
       if (RR) {
         const cx<T> rxp = rr_x1<3>(vp);
         if (odd) {
