@@ -41,6 +41,8 @@
 #ifndef ELH_H
 #define ELH_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -324,7 +326,27 @@ int elh_batch_destroy(elh_batch* b);
 int elh_gradient(elh_handle* h, int nrhs, const void* u, const void* v,
                  double* g_lam, double* g_mu, double* g_rho);
 
-/* Number of levels, cells per axis (x-order) and spacing of `level`. */
+/* Receivers of an FWI misfit (the adjoint-state setting that motivates the
+ * solver, Section 1).  A receiver samples one unknown of the level-0 vector;
+ * idx: (device) int64 storage indices into one vector of (dim+1)*n cells,
+ * distinct; an index outside the vector samples zero and is skipped by the
+ * injection.
+ * elh_receivers: d[s][i] = u[s][idx[i]] - dobs[s][i] (P_r u - d_obs; dobs
+ *   may be NULL for plain sampling), u: nrhs complex128 vectors, dobs and d:
+ *   (nrhs, nrec) complex128; phi (device, may be NULL): nrhs + 1 doubles,
+ *   phi[s] = 1/2 sum_i |d[s][i]|^2 (the misfit of source s, fixed-order
+ *   reduction) and phi[nrhs] = sum_s phi[s] (the total misfit).
+ * elh_inject: v = scale P_r^T r, i.e. v[s] = 0 except v[s][idx[i]] =
+ *   scale r[s][i] (the adjoint source); r: (nrhs, nrec), v: nrhs complex128
+ *   vectors (overwritten).
+ * Both run on the handle's stream and return without synchronising.
+ * Errors: ELH_ERR_ARG on sizes, NULL pointers or a non-finite scale. */
+int elh_receivers(elh_handle* h, int nrhs, const void* u, int nrec,
+                  const int64_t* idx, const void* dobs, void* d, double* phi);
+int elh_inject(elh_handle* h, int nrhs, int nrec, const int64_t* idx,
+               const void* r, double scale, void* v);
+
+/* Number of levels, cells per axis (x-order) and spacing of `level`. *//* Number of levels, cells per axis (x-order) and spacing of `level`. */
 int elh_level_info(elh_handle* h, int level, int* n3, double* hl);
 
 /* Stencil autotuner (batching / set-up row of the hot path).  On its first

@@ -17,6 +17,7 @@ EXPORTED = [
     "elh_vcycle", "elh_solve", "elh_solve_adjoint", "elh_solve_batch", "elh_gradient",
     "elh_level_info", "elh_stencil_choice", "elh_status_string", "elh_last_error",
     "elh_batch_create", "elh_batch_size", "elh_batch_handle", "elh_batch_solve", "elh_batch_destroy",
+    "elh_receivers", "elh_inject",
 ]
 
 
@@ -94,6 +95,8 @@ def load():
         "elh_batch_solve": [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_void_p),
                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
         "elh_batch_destroy": [vp],
+        "elh_receivers": [H, ip, vp, ip, vp, vp, vp, vp],
+        "elh_inject": [H, ip, ip, vp, vp, ctypes.c_double, vp],
         "elh_status_string": [ip],
         "elh_last_error": [],
     }

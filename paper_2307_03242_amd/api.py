@@ -289,9 +289,10 @@ class Problem:
 
     @staticmethod
     def solve_batch(problems, qs, restart=5, maxit=500, rtol=1e-6):
-        """Solve independent problems together (one host thread each; create
-        the problems on different streams so their kernels overlap).
-        Returns (list of u, list of info lists, code)."""
+        """Solve independent problems together: the library drives them in
+        lockstep from the calling thread (create the problems on different
+        streams so their kernels overlap).  Returns (list of u, list of info
+        lists, code)."""
         if len(problems) != len(qs) or not problems:
             raise ValueError("one right-hand-side batch per problem")
         lib = problems[0].lib
@@ -319,6 +320,56 @@ class Problem:
             infos.append([_info(s) for s in stats[k:k + r]])
             k += r
         return us, infos, code
+
+    # -- receivers (misfit and adjoint source) --------------------------------
+    def receiver_indices(self, mask):
+        """int64 storage indices (into one level-0 vector) of the True
+        entries of a boolean receiver mask of the vector's shape."""
+        full = (self.dim + 1,) + self.shape
+        if mask.dtype != torch.bool or tuple(mask.shape) != full:
+            raise ValueError("receiver mask must be a bool tensor of shape %s" % (full,))
+        return torch.nonzero(mask.reshape(-1)).reshape(-1).to(device=self.device, dtype=torch.int64)
+
+    def _idx(self, idx):
+        if (idx.dtype != torch.int64 or idx.dim() != 1 or idx.numel() < 1 or not idx.is_cuda
+                or idx.device != self.device or not idx.is_contiguous()):
+            raise ValueError("receiver indices must be a non-empty contiguous int64 vector on %s" % self.device)
+        return idx
+
+    def receivers(self, u, idx, d_obs=None, misfit=False):
+        """d = P_r u - d_obs (d_obs optional), shape (nrhs, nrec); with
+        misfit=True also phi (nrhs + 1 float64: 1/2 |d_s|^2 per source,
+        then their total)."""
+        if u.dtype != torch.complex128:
+            raise TypeError("wavefields must be complex128")
+        nrhs = self._vec(u, 0)
+        idx = self._idx(idx)
+        d = torch.empty((nrhs, idx.numel()), dtype=torch.complex128, device=self.device)
+        if d_obs is not None:
+            if d_obs.dim() == 1 and u.dim() == self.dim + 1:
+                d_obs = d_obs.reshape(1, -1)
+            self._same(d_obs, d, "d_obs")
+        phi = torch.empty(nrhs + 1, dtype=torch.float64, device=self.device) if misfit else None
+        L.check(self.lib.elh_receivers(self.handle, nrhs, _ptr(u), idx.numel(), _ptr(idx), _ptr(d_obs), _ptr(d),
+                                       _ptr(phi)))
+        if u.dim() == self.dim + 1:
+            d = d[0]
+        return (d, phi) if misfit else d
+
+    def inject(self, r, idx, scale=1.0):
+        """v = scale P_r^T r: zero vectors with r at the receivers; r has
+        shape (nrhs, nrec) (or (nrec,) for one vector)."""
+        idx = self._idx(idx)
+        if r.dtype != torch.complex128 or not r.is_cuda or r.device != self.device or not r.is_contiguous():
+            raise ValueError("receiver values must be a contiguous complex128 tensor on %s" % self.device)
+        one = r.dim() == 1
+        if r.shape[-1] != idx.numel() or r.dim() not in (1, 2):
+            raise ValueError("receiver values must have shape (nrhs, %d)" % idx.numel())
+        nrhs = 1 if one else r.shape[0]
+        full = (self.dim + 1,) + self.shape
+        v = torch.empty(full if one else (nrhs,) + full, dtype=torch.complex128, device=self.device)
+        L.check(self.lib.elh_inject(self.handle, nrhs, idx.numel(), _ptr(idx), _ptr(r), float(scale), _ptr(v)))
+        return v
 
     def gradient(self, u, v):
         if u.dtype != torch.complex128:

@@ -2334,6 +2334,27 @@ extern "C" int elh_gradient(elh_handle* H, int nrhs, const void* u, const void* 
   return 0;
 }
 
+extern "C" int elh_receivers(elh_handle* H, int nrhs, const void* u, int nrec, const int64_t* idx, const void* dobs,
+                             void* d, double* phi) {
+  int rc = check_common(H, 0, ELH_C128, nrhs);
+  if (rc) return rc;
+  if (nrec < 1 || !u || !idx || !d) return fail(ELH_ERR_ARG, "u, idx and d must be non-NULL and nrec >= 1");
+  CHK(launch_rec_sample(H->lv[0].vs, nrec, idx, u, dobs, d, phi, nrhs, H->st));
+  return 0;
+}
+
+extern "C" int elh_inject(elh_handle* H, int nrhs, int nrec, const int64_t* idx, const void* r, double scale,
+                          void* v) {
+  int rc = check_common(H, 0, ELH_C128, nrhs);
+  if (rc) return rc;
+  if (nrec < 1 || !idx || !r || !v) return fail(ELH_ERR_ARG, "idx, r and v must be non-NULL and nrec >= 1");
+  if (nrhs > 65535) return fail(ELH_ERR_ARG, "at most 65535 right-hand sides");
+  if (!std::isfinite(scale)) return fail(ELH_ERR_ARG, "scale must be finite");
+  CHK(launch_zero(v, (int64_t)nrhs * H->lv[0].vs * 16, H->st));
+  CHK(launch_rec_inject(H->lv[0].vs, nrec, idx, r, scale, v, nrhs, H->st));
+  return 0;
+}
+
 extern "C" const char* elh_status_string(int s) {
   switch (s) {
     case ELH_OK: return "ok";

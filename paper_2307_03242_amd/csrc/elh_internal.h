@@ -97,6 +97,11 @@ int launch_dense_invert(int64_t N, void* A, void* B, void* col, int* piv, hipStr
 template <typename T>
 int launch_dense_mv(int64_t N, const void* Q, int transposed, int cj, const void* b, void* x, int nrhs,
                     hipStream_t st);
+// receivers: d = P_r u (- dobs), phi = 1/2 |d|^2 per rhs and their total (optional); v[idx] = scale r
+int launch_rec_sample(int64_t vs, int nrec, const int64_t* idx, const void* u, const void* dobs, void* d, double* phi,
+                      int nrhs, hipStream_t st);
+int launch_rec_inject(int64_t vs, int nrec, const int64_t* idx, const void* r, double scale, void* v, int nrhs,
+                      hipStream_t st);
 int launch_gradient(const LevelArgs<double>& L, int dim, int nrhs, const void* u, const void* v, double* gl,
                     double* gm, double* gr, hipStream_t st);
 // Hybrid Kaczmarz on the Schur complement of the pressure at the coarsest

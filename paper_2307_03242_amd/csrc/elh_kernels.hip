@@ -1353,6 +1353,79 @@ int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStre
 }
 
 // ---------------------------------------------------------------------------
+// Receivers of the FWI misfit: the restriction P_r samples a wavefield at a
+// list of storage indices (one unknown each), the injection P_r^T scatters
+// receiver values back into a zero wavefield.  Indices outside the vector
+// are skipped (sampled as zero).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rec_sample(int64_t vs, int nrec, const int64_t* __restrict__ idx,
+                                                     const cx<double>* __restrict__ u,
+                                                     const cx<double>* __restrict__ dobs, cx<double>* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (i >= nrec) return;
+  const int64_t j = idx[i];
+  cx<double> v = (j >= 0 && j < vs) ? u[(int64_t)s * vs + j] : czero<double>();
+  if (dobs) v = v - dobs[(int64_t)s * nrec + i];
+  d[(int64_t)s * nrec + i] = v;
+}
+
+// phi[s] = 1/2 sum_i |r[s][i]|^2, one block per rhs, fixed-order tree
+__global__ void __launch_bounds__(256) k_rec_half_norm2(int nrec, const cx<double>* __restrict__ r,
+                                                         double* __restrict__ phi) {
+  __shared__ double red[256];
+  const int s = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nrec; i += 256) acc += abs2(r[(int64_t)s * nrec + i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) phi[s] = 0.5 * red[0];
+}
+
+// phi[nrhs] = sum of phi[0..nrhs) in order (the total misfit)
+__global__ void k_rec_total(int nrhs, double* __restrict__ phi) {
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int s = 0; s < nrhs; ++s) t += phi[s];
+  phi[nrhs] = t;
+}
+
+__global__ void __launch_bounds__(256) k_rec_inject(int64_t vs, int nrec, const int64_t* __restrict__ idx,
+                                                     const cx<double>* __restrict__ r, double scale,
+                                                     cx<double>* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (i >= nrec) return;
+  const int64_t j = idx[i];
+  const cx<double> a = r[(int64_t)s * nrec + i];
+  if (j >= 0 && j < vs) v[(int64_t)s * vs + j] = mk(scale * a.re, scale * a.im);
+}
+
+int launch_rec_sample(int64_t vs, int nrec, const int64_t* idx, const void* u, const void* dobs, void* d, double* phi,
+                      int nrhs, hipStream_t st) {
+  if (nrec < 1 || nrhs < 1 || nrhs > 65535) return (int)hipErrorInvalidValue;
+  ELH_LAUNCH(k_rec_sample, dim3((nrec + 255) / 256, nrhs), dim3(256), 0, st, vs, nrec, idx, (const cx<double>*)u,
+             (const cx<double>*)dobs, (cx<double>*)d);
+  if (phi) {
+    ELH_LAUNCH(k_rec_half_norm2, dim3(nrhs), dim3(256), 0, st, nrec, (const cx<double>*)d, phi);
+    ELH_LAUNCH(k_rec_total, dim3(1), dim3(64), 0, st, nrhs, phi);
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_rec_inject(int64_t vs, int nrec, const int64_t* idx, const void* r, double scale, void* v, int nrhs,
+                      hipStream_t st) {
+  if (nrec < 1 || nrhs < 1 || nrhs > 65535) return (int)hipErrorInvalidValue;
+  ELH_LAUNCH(k_rec_inject, dim3((nrec + 255) / 256, nrhs), dim3(256), 0, st, vs, nrec, idx, (const cx<double>*)r,
+             scale, (cx<double>*)v);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Outer flexible GMRES with its bookkeeping on the device, one thread per
 // right-hand side.  The basis stays unnormalised as in the host driver:
 // V_i = v_i / sig_i, h_ij = sig_i sig_j <V_i, A Z_j>, h_{j+1,j} = sig_j

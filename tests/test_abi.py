@@ -149,3 +149,18 @@ def test_create_rejects_a_singular_shift_without_gpu():
         d.gamma, d.alpha, d.omega = g, a, om
         assert lib.elh_create(ctypes.byref(d), dummy, dummy, dummy, None, ctypes.byref(h)) == _lib.ELH_ERR_ARG
         assert not h.value
+
+
+def test_receiver_binding_checks_without_gpu():
+    """receiver indices must be a device int64 vector, the mask a bool
+    tensor of the vector's shape: ValueError before any library call"""
+    import torch
+    p = _cpu_problem()
+    with pytest.raises(ValueError):
+        p.receiver_indices(torch.zeros((4, 4, 4, 4), dtype=torch.int32))
+    with pytest.raises(ValueError):
+        p.receiver_indices(torch.zeros((3, 4, 4, 4), dtype=torch.bool))
+    with pytest.raises(ValueError):
+        p._idx(torch.arange(3))          # host tensor
+    with pytest.raises(ValueError):
+        p.inject(torch.zeros(3, dtype=torch.complex128), torch.arange(3))
