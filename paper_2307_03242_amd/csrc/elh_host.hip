@@ -1609,7 +1609,11 @@ struct OuterSolve {
   std::unique_ptr<PhaseTimer> tm;
   int iters = 0, j = 0;
   bool in_restart = false, done = false;
-  int64_t vstr() const { return (int64_t)np * len; }
+  // basis vectors sit 1 MiB + 8 KiB (complex128) apart beyond their packed
+  // length: at power-of-two strides the Gram-Schmidt kernels' streams (one
+  // per basis vector, same offsets) lose 5-10 % of their bandwidth
+  static constexpr int64_t kPad = 66048;
+  int64_t vstr() const { return (int64_t)np * len + kPad; }
   cx<double>* V(int i) const { return (cx<double>*)ws->V.p + i * vstr(); }
   void* Z(int i) const { return (char*)ws->Z.p + i * vstr() * (z32 ? 8 : 16); }
 };
@@ -1630,7 +1634,9 @@ static int os_begin(OuterSolve& S) {
   elh_handle* H = S.H;
   const int n = S.nrhs;
   const size_t vb = (size_t)n * S.len * 16;
-  if (ensure(S.ws->V, vb * (S.m + 1)) || ensure(S.ws->Z, (size_t)n * S.len * (S.z32 ? 8 : 16) * S.m))
+  const size_t vpad = (size_t)OuterSolve::kPad;
+  if (ensure(S.ws->V, (vb + vpad * 16) * (S.m + 1)) ||
+      ensure(S.ws->Z, ((size_t)n * S.len + vpad) * (S.z32 ? 8 : 16) * S.m))
     return ELH_ERR_OOM;
   S.np = n;
   S.map.resize(n);
