@@ -1467,8 +1467,8 @@ static int cycle(elh_handle* H, int l, bool adj, const void* b, void* x, int nrh
     CHK((launch_multidot<CT, CT>(3, V1, vec, C.vs, V2, C.vs, C.vs, nrhs, kp, f2 ? nullptr : kd, H->st)));
     CHK(launch_kcycle_coef(2, f2 ? nullptr : kd, f2 ? kp : nullptr, multidot_blocks(3, C.vs, FUSE_BLOCKS), kc2, ks, nrhs,
                               H->st));
-    CHK(launch_zero(C.x[prec].p, (int64_t)nrhs * C.vs * csz(prec), H->st));
-    CHK((launch_multiaxpy<CT, CT>(2, kc2, E1, 4 * vec, C.vs, C.x[prec].p, C.vs, C.vs, nrhs, H->st)));
+    // e = coef0 E1 + coef1 E2 written, not added (E2 = E1 + 4 vec)
+    CHK((launch_multiaxpy<CT, CT>(2, kc2, E1, 4 * vec, C.vs, C.x[prec].p, C.vs, C.vs, nrhs, H->st, true)));
   } else {
     CHK(op_restrict_residual<T>(H, l, adj, xr, b, C.b[prec].p, nrhs));
     CHK(cycle<T>(H, l + 1, adj, C.b[prec].p, C.x[prec].p, nrhs));
