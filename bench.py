@@ -309,6 +309,45 @@ def extras(args):
         "workload": "128^3, true medium seed 500, start = true with an 8%% central Gaussian anomaly, 8 sources, "
                     "receivers on the plane at depth 18; forward + adjoint solves to %.0e + gradient kernel" % args.rtol,
         "seconds": tg, "misfit": float(phi.item())}
+
+    # one GPU's share of the 256^3 grid split into x_3 slabs over 8 GPUs:
+    # 256 x 256 x 32 cells plus a one-plane halo on each side, the kernels
+    # at that shape (HIP events on the library's stream)
+    from synthetic import random_field
+    sh = (34, 256, 256)
+    ms_, meds = media(sh, 3)
+    ps = Problem(*meds, precond_dtype=torch.complex64, h=1.0, omega=omega_for_ppw(ms_["vs"].min(), 1.0, 10),
+                 gamma=0.01, alpha=args.alpha, beta=2 / 3, abl_width=args.abl * 1.0, abl_amp=2.0, levels=2,
+                 cycle="K", coarse_mode="relax", coarse_sweeps=1)
+    ncell = 34 * 256 * 256
+    st = torch.cuda.current_stream()
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    x32 = torch.from_numpy(random_field(sh, 1)).cuda().to(torch.complex64)
+    b32 = torch.from_numpy(random_field(sh, 2)).cuda().to(torch.complex64)
+    r32 = torch.empty_like(x32)
+    x64 = x32.to(torch.complex128)
+    y64 = torch.empty_like(x64)
+    t_res = timed(lambda: ps.residual(b32, x32, shifted=True, out=r32))
+    t_app = timed(lambda: ps.apply(x64, out=y64))
+    t_rel = timed(lambda: ps.relax(b32, r32, 0))
+    out["shard_slab"] = {
+        "workload": "256 x 256 x 34 cells (one of 8 x_3 slabs of 256^3 with a one-plane halo each side), seed 3 media",
+        "residual_f32_ms": t_res, "residual_f32_GBps": RESID_BYTES_F32 * ncell / (t_res * 1e-3) / 1e9,
+        "apply_f64_ms": t_app, "apply_f64_GBps": APPLY_BYTES_F64 * ncell / (t_app * 1e-3) / 1e9,
+        "half_sweep_f32_ms": t_rel}
+    del ps, x32, b32, r32, x64, y64
+    torch.cuda.empty_cache()
     return out
 
 
