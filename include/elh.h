@@ -339,8 +339,10 @@ int elh_gradient(elh_handle* h, int nrhs, const void* u, const void* v,
  * elh_inject: v = scale P_r^T r, i.e. v[s] = 0 except v[s][idx[i]] =
  *   scale r[s][i] (the adjoint source); r: (nrhs, nrec), v: nrhs complex128
  *   vectors (overwritten).
- * Both run on the handle's stream and return without synchronising.
- * Errors: ELH_ERR_ARG on sizes, NULL pointers or a non-finite scale. */
+ * Both run on the handle's stream and return without synchronising.  The
+ * output must not overlap the inputs (d = u or v = r is rejected).
+ * Errors: ELH_ERR_ARG on sizes, NULL pointers, aliased outputs or a
+ * non-finite scale. */
 int elh_receivers(elh_handle* h, int nrhs, const void* u, int nrec,
                   const int64_t* idx, const void* dobs, void* d, double* phi);
 int elh_inject(elh_handle* h, int nrhs, int nrec, const int64_t* idx,

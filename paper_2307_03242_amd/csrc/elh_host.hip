@@ -2345,6 +2345,7 @@ extern "C" int elh_receivers(elh_handle* H, int nrhs, const void* u, int nrec, c
   int rc = check_common(H, 0, ELH_C128, nrhs);
   if (rc) return rc;
   if (nrec < 1 || !u || !idx || !d) return fail(ELH_ERR_ARG, "u, idx and d must be non-NULL and nrec >= 1");
+  if (d == u || (const void*)d == (const void*)idx) return fail(ELH_ERR_ARG, "d must not alias u or idx");
   CHK(launch_rec_sample(H->lv[0].vs, nrec, idx, u, dobs, d, phi, nrhs, H->st));
   return 0;
 }
@@ -2354,6 +2355,7 @@ extern "C" int elh_inject(elh_handle* H, int nrhs, int nrec, const int64_t* idx,
   int rc = check_common(H, 0, ELH_C128, nrhs);
   if (rc) return rc;
   if (nrec < 1 || !idx || !r || !v) return fail(ELH_ERR_ARG, "idx, r and v must be non-NULL and nrec >= 1");
+  if (v == r || (const void*)v == (const void*)idx) return fail(ELH_ERR_ARG, "v must not alias r or idx");
   if (nrhs > 65535) return fail(ELH_ERR_ARG, "at most 65535 right-hand sides");
   if (!std::isfinite(scale)) return fail(ELH_ERR_ARG, "scale must be finite");
   CHK(launch_zero(v, (int64_t)nrhs * H->lv[0].vs * 16, H->st));

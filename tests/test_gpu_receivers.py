@@ -119,6 +119,8 @@ def test_receiver_entry_points_reject_bad_arguments():
     assert lib.elh_receivers(prob.handle, 1, None, 4, p(idx), None, p(d), None) == L.ELH_ERR_ARG
     assert lib.elh_inject(prob.handle, 1, 4, p(idx), p(d), float("nan"), p(u)) == L.ELH_ERR_ARG
     assert lib.elh_inject(prob.handle, 1, 4, None, p(d), 1.0, p(u)) == L.ELH_ERR_ARG
+    assert lib.elh_receivers(prob.handle, 1, p(u), 4, p(idx), None, p(u), None) == L.ELH_ERR_ARG
+    assert lib.elh_inject(prob.handle, 1, 4, p(idx), p(u), 1.0, p(u)) == L.ELH_ERR_ARG
     with pytest.raises(ValueError):
         prob.receivers(u, idx.to(torch.int32))
     with pytest.raises(ValueError):
