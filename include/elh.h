@@ -162,7 +162,12 @@ typedef struct elh_handle elh_handle;
  * coarse hierarchy (media means, kappa = 1/(lam+mu), float32 copies) and,
  * for ELH_COARSE_DENSE, the coarsest-level inverse.  stream: hipStream_t
  * (NULL = default stream).  Section 3.1 (operator), Section 3.2 (hierarchy
- * by re-discretisation). */
+ * by re-discretisation).
+ * Environment, read here: ELH_GRAPHS=0 runs the cycles and Gram-Schmidt
+ * steps eagerly instead of as replayed hipGraphs; ELH_ZCHUNK=c sets the
+ * marching kernels' default x_3 chunk (c > 0, shortened on small grids) or
+ * forces exactly -c planes (c < 0); ELH_TUNE / ELH_TUNE_CACHE: see
+ * elh_stencil_choice.  None of them changes results. */
 int elh_create(const elh_desc* desc, const double* lam, const double* mu,
                const double* rho, void* stream, elh_handle** out);
 
