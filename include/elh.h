@@ -289,11 +289,12 @@ int elh_solve_adjoint(elh_handle* h, int nrhs, const void* r, void* v,
 /* Solve several independent problems together: problem i (handle h[i],
  * any grid size) solves nrhs[i] right-hand sides q[i] -> u[i] exactly as
  * elh_solve would (same iterates, bitwise).  The calling thread drives all
- * problems in lockstep: every FGMRES iteration enqueues each unfinished
- * problem's cycle, outer operator and Gram-Schmidt step before it waits for
- * any of their statuses, so the kernels of problems created on different
- * streams overlap on the GPU; a problem leaves the lockstep when its
- * right-hand sides have converged.  stats: (host) sum(nrhs) records in
+ * problems: each unfinished problem has one FGMRES iteration (cycle, outer
+ * operator, Gram-Schmidt step) in flight on its handle's stream, and the
+ * thread polls the streams, enqueueing a problem's next iteration as soon as
+ * its status has arrived, so the kernels of problems created on different
+ * streams overlap on the GPU; a problem leaves when its right-hand sides
+ * have converged.  stats: (host) sum(nrhs) records in
  * problem order, may be NULL.  Returns the most severe status of all
  * problems (a negative one names its problem in elh_last_error). */
 int elh_solve_batch(int nprob, elh_handle* const* h, const int* nrhs,

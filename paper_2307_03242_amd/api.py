@@ -289,10 +289,10 @@ class Problem:
 
     @staticmethod
     def solve_batch(problems, qs, restart=5, maxit=500, rtol=1e-6):
-        """Solve independent problems together: the library drives them in
-        lockstep from the calling thread (create the problems on different
-        streams so their kernels overlap).  Returns (list of u, list of info
-        lists, code)."""
+        """Solve independent problems together: the library drives them from
+        the calling thread, one iteration of each in flight (create the
+        problems on different streams so their kernels overlap).  Returns
+        (list of u, list of info lists, code)."""
         if len(problems) != len(qs) or not problems:
             raise ValueError("one right-hand-side batch per problem")
         lib = problems[0].lib
@@ -383,8 +383,9 @@ class Problem:
 
 class Batch:
     """Problems of uneven grid sizes solved together (elh_batch_*): each
-    problem gets a library-owned stream, and solve() drives all of them in
-    lockstep from the calling thread, so their kernels overlap on the GPU.
+    problem gets a library-owned stream, and solve() drives all of them from
+    the calling thread, one iteration of each in flight, so their kernels
+    overlap on the GPU.
 
     problems: list of dicts with keys lam, mu, rho (float64 tensors, numpy
     grid shape) and the Problem keyword parameters.  problem(i) returns a

@@ -16,6 +16,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/elh.h"
@@ -1578,7 +1579,7 @@ static bool graphs_ok(const elh_handle* H) {
 // restart the right-hand sides that have converged leave: the rest are packed
 // into leading slots, so later cycles and operator applies skip them.  The
 // solve is a resumable state machine, so that one host thread can drive
-// several problems in lockstep (elh_solve_batch).
+// several problems side by side (elh_solve_batch).
 // ---------------------------------------------------------------------------
 struct OuterOps {
   std::function<int(const void* v, void* z, int n)> M;                  // z = M v
@@ -2159,11 +2160,11 @@ extern "C" int elh_solve_adjoint(elh_handle* H, int nrhs, const void* r, void* v
   return solve_impl(H, true, nrhs, r, v, opts, stats);
 }
 
-// Several problems in lockstep from one host thread: every iteration
-// enqueues each unfinished problem's cycle, operator and Gram-Schmidt step on
-// its own stream before waiting for any status, so the problems' kernels run
-// side by side on the GPU; a problem leaves the lockstep when its rhs have
-// converged.
+// Several problems from one host thread: each unfinished problem has one
+// iteration (cycle, operator and Gram-Schmidt step) in flight on its own
+// stream, and the host polls the streams, finishing and re-enqueueing each
+// problem as its status arrives, so the problems' kernels run side by side
+// on the GPU; a problem leaves when its rhs have converged.
 static int batch_drive(int nprob, elh_handle* const* hs, const int* nrhs, const void* const* q, void* const* u,
                        const elh_solve_opts* opts, elh_solve_stats* stats) {
   if (nprob < 1 || !hs || !nrhs || !q || !u || !opts) return fail(ELH_ERR_ARG, "invalid batch arguments");
@@ -2194,23 +2195,36 @@ static int batch_drive(int nprob, elh_handle* const* hs, const int* nrhs, const 
     if (failed(i, rc)) continue;
     failed(i, os_begin(S[i]));
   }
+  // each problem's next iteration is enqueued as soon as its own status
+  // has arrived (its stream is idle), not when the whole round has: the
+  // small problems do not wait for the largest one's iterations
+  std::vector<char> queued(nprob, 0);
+  auto enqueue = [&](int i) {
+    int rc = S[i].in_restart ? 0 : os_restart_begin(S[i]);
+    if (!rc) rc = os_iter_enqueue(S[i]);
+    if (rc > 0) rc = fail(ELH_ERR_HIP, "launch failed");
+    if (!failed(i, rc)) queued[i] = 1;
+  };
+  for (int i = 0; i < nprob; ++i)
+    if (!S[i].done) enqueue(i);
   for (;;) {
-    std::vector<int> run;
-    for (int i = 0; i < nprob; ++i)
-      if (!S[i].done) run.push_back(i);
-    if (run.empty()) break;
-    for (int i : run) {
-      int rc = S[i].in_restart ? 0 : os_restart_begin(S[i]);
-      if (!rc) rc = os_iter_enqueue(S[i]);
+    bool pending = false, progressed = false;
+    for (int i = 0; i < nprob; ++i) {
+      if (S[i].done || !queued[i]) continue;
+      pending = true;
+      // not ready yet: look again later; any other answer (done, or an
+      // error, which the synchronisation in os_iter_finish reports) ends
+      // this iteration
+      if (hipStreamQuery(S[i].H->st) == hipErrorNotReady) continue;
+      queued[i] = 0;
+      progressed = true;
+      int rc = os_iter_finish(S[i]);
       if (rc > 0) rc = fail(ELH_ERR_HIP, "launch failed");
-      failed(i, rc);
+      if (failed(i, rc) || S[i].done) continue;
+      enqueue(i);
     }
-    for (int i : run)
-      if (!S[i].done) {
-        int rc = os_iter_finish(S[i]);
-        if (rc > 0) rc = fail(ELH_ERR_HIP, "launch failed");
-        failed(i, rc);
-      }
+    if (!pending) break;
+    if (!progressed) std::this_thread::yield();
   }
   for (int i = 0; i < nprob; ++i)
     if (!rcs[i]) {
