@@ -212,7 +212,7 @@ def extras(args):
         "fp64_batched_solves_per_s": 32 / tb64, "speedup_vs_fp64_batched": tb64 / tb, "fp64_batched_code": code64b}
 
     # 12 independent problems of uneven size in one batch handle (a library
-    # stream each, driven in lockstep), against the same problems solved one
+    # stream each, driven side by side), against the same problems solved one
     # after another through their own handles
     from paper_2307_03242_amd import Batch
     sizes = [64, 80, 96, 112, 128, 144, 160, 176, 192, 96, 128, 160]

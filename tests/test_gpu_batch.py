@@ -1,5 +1,5 @@
 """Batching forms through the C ABI: the uneven-grid batch handle
-(elh_batch_*) solving problems of different sizes in lockstep, and
+(elh_batch_*) solving problems of different sizes side by side, and
 right-hand sides that converge at different restarts (they leave the packed
 batch).  Expected values: the oracle's true residuals, and the same solves
 run one at a time (a problem of a batch runs the same kernels in the same
