@@ -14,7 +14,7 @@ value is the solve rate with the float32 cycle; the same solve with the
 float64 cycle is timed beside it.
 
 Prints ONE JSON line (rank 0).  `python bench.py --gpus N` with N > 1 exits:
-this build runs on one GPU.
+the library and this benchmark run on one GPU.
 """
 import argparse
 import json
@@ -470,7 +470,7 @@ def paper_3d(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(each source/problem would shard independently across GPUs).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -585,7 +585,7 @@ def main():
     resid_gbs = RESID_BYTES_F32 * n ** 3 / (resid_ms * 1e-3) / 1e9
     del x, xx, bb, rr
 
-    # the benchmark spec's cycle as written: 4-level V(1,1), float32 against
+    # the plain V-cycle: 4-level V(1,1), float32 against
     # float64 (a short untimed solve that tunes and records the graphs, then
     # one timed solve with up to 1500 iterations)
     vcyc = {}
