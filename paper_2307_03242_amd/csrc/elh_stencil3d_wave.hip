@@ -7,7 +7,9 @@
 //    segment and marches along x_3; wavefront k computes the rows of
 //    u_{k+1} (the u-u block of H is diagonal in the component) and its
 //    term of the divergence in the p row; lanes 0 and 63 are halo lanes
-//    (62 outputs per wavefront);
+//    (62 outputs per wavefront); a remainder of at most 14 cells at the end
+//    of the rows goes to workgroups whose wavefronts split into four 16-lane
+//    groups, one row each (at n_1 = 256: 4.25 wavefronts per row, not 5);
 //  * neighbours along x_1 are other lanes of the same wavefront, read with
 //    DPP wavefront shifts;
 //  * neighbours along x_2 (rows c-1, c+1; rho also at c-2) are loaded
@@ -31,6 +33,11 @@ namespace {
 
 constexpr int WV_LANES = 64;
 constexpr int WV_OUT = WV_LANES - 2;   // outputs per wave along x_1
+// x_1 remainders of at most RG_OUT cells go to wavefronts of four 16-lane
+// groups, one x_2 row each (14 outputs per group)
+constexpr int RG_LANES = 16;
+constexpr int RG_OUT = RG_LANES - 2;
+constexpr int RG_ROWS = WV_LANES / RG_LANES;
 
 // DPP wavefront shifts: FROM_LEFT gives lane i the value of lane i-1,
 // FROM_RIGHT the value of lane i+1 (zero where that lane does not exist).
@@ -52,6 +59,18 @@ template <typename T> __device__ __forceinline__ T fromL(T v) { return dpp<DPP_W
 template <typename T> __device__ __forceinline__ T fromR(T v) { return dpp<DPP_WAVE_SHL1>(v); }
 template <typename T> __device__ __forceinline__ cx<T> fromL(cx<T> v) { return mk(fromL(v.re), fromL(v.im)); }
 template <typename T> __device__ __forceinline__ cx<T> fromR(cx<T> v) { return mk(fromR(v.re), fromR(v.im)); }
+// The same shifts inside lane groups of G lanes (G = 64: the whole
+// wavefront; G = 16: DPP rows), zero at the group's edges.
+constexpr int DPP_ROW_SHL1 = 0x101;
+constexpr int DPP_ROW_SHR1 = 0x111;
+template <int G, typename T> __device__ __forceinline__ T gL(T v) {
+  return dpp<G == 64 ? DPP_WAVE_SHR1 : DPP_ROW_SHR1>(v);
+}
+template <int G, typename T> __device__ __forceinline__ T gR(T v) {
+  return dpp<G == 64 ? DPP_WAVE_SHL1 : DPP_ROW_SHL1>(v);
+}
+template <int G, typename T> __device__ __forceinline__ cx<T> gL(cx<T> v) { return mk(gL<G>(v.re), gL<G>(v.im)); }
+template <int G, typename T> __device__ __forceinline__ cx<T> gR(cx<T> v) { return mk(gR<G>(v.re), gR<G>(v.im)); }
 
 // amp * (delta/width)^2, delta the distance into the absorbing layer at
 // physical coordinate xp along an axis of physical length len.
@@ -151,18 +170,21 @@ __device__ __forceinline__ void rr_emit(const W3Ctx<T>& C, int I3, cx<T> rz, cx<
 
 // Per-wavefront context of the march: tile coordinates, clamped row
 // offsets, buffer resources, constants, gamma~ of this wavefront's faces.
-template <typename T, typename TI, bool RESID>
+// G: lanes per x_1 segment (64, or 16 with one x_2 row per group; c2 is
+// then the lane's row, and rows at or beyond n_2 store nothing)
+template <typename T, typename TI, bool RESID, int G = WV_LANES>
 __device__ __forceinline__ void w3_setup(W3Ctx<T>& C, const LevelArgs<T>& L, const cx<TI>* __restrict__ x,
                                          const cx<T>* __restrict__ b, cx<T>* __restrict__ y, int c1o, int k, int c2,
                                          int tz, int zc, int s) {
   C.n1 = L.n[0]; C.n2 = L.n[1]; C.n3 = L.n[2];
   C.plane = C.n1 * C.n2;
-  C.c1 = c1o + (int)threadIdx.x;
+  const int gl = (int)threadIdx.x & (G - 1);
+  C.c1 = c1o + gl;
   C.c2 = c2;
   C.z0 = tz * zc;
   C.z1 = min(C.z0 + zc, C.n3);
   C.inx = C.c1 >= 0 && C.c1 < C.n1;
-  C.outlane = threadIdx.x >= 1 && threadIdx.x <= WV_OUT && C.inx;
+  C.outlane = gl >= 1 && gl <= G - 2 && C.inx && c2 < C.n2;
   const int cc1 = min(max(C.c1, 0), C.n1 - 1);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -208,8 +230,9 @@ __device__ __forceinline__ void w3_setup(W3Ctx<T>& C, const LevelArgs<T>& L, con
 // the coarse level instead of stored; the march then takes its planes in
 // (odd, even) pairs from 2 Z0 - 3, so that the residual of plane 2 Z0 - 1,
 // which the x_3 full weighting of u_3 needs, is exact.
-template <int K, typename T, typename TI, bool RESID, bool RR = false>
+template <int K, typename T, typename TI, bool RESID, bool RR = false, int G = WV_LANES>
 __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
+  static_assert(G == WV_LANES || !RR, "the fused restriction marches whole wavefronts");
   constexpr int CB = (int)sizeof(cx<T>), CBI = (int)sizeof(cx<TI>), RBY = (int)sizeof(T);
   const T q = T(0.25), hf = T(0.5);
   const T beta = C.beta;
@@ -336,7 +359,7 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
     // face means of rho for this component at rows c-1, c, c+1
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      if (K == 0) rf[r] = hf * ((r == 1 ? nrhoL : fromL(rhon[r])) + rhon[r]);
+      if (K == 0) rf[r] = hf * ((r == 1 ? nrhoL : gL<G>(rhon[r])) + rhon[r]);
       if (K == 1) rf[r] = hf * (nrho[r] + rhon[r]);
       if (K == 2) rf[r] = hf * (rhob[r] + rhon[r]);
     }
@@ -348,7 +371,7 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
     const cx<T> Wmpn = rf[0] * Un[0] + rf[2] * Un[2];
     // Y_3(t+1) = beta u + (1-beta) A_1 A_2 u at row c
     const cx<T> V = q * (Un[0] + Un[2]) + hf * Un[1];
-    const cx<T> Y3n = beta * Un[1] + oq * (fromL(V) + fromR(V)) + oh * V;
+    const cx<T> Y3n = beta * Un[1] + oq * (gL<G>(V) + gR<G>(V)) + oh * V;
     // A_3 u(t) at rows c-1, c, c+1; Y_1(t) (row c) and Y_2(t) (three rows)
     cx<T> Z[3];
 #pragma unroll
@@ -356,9 +379,9 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
     const cx<T> y1 = beta * UC[1] + oq * (Z[0] + Z[2]) + oh * Z[1];
     cx<T> y2[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) y2[r] = beta * UC[r] + oq * (fromL(Z[r]) + fromR(Z[r])) + oh * Z[r];
-    const cx<T> d1lo = y1 - fromL(y1);
-    const cx<T> d1hi = fromR(d1lo);
+    for (int r = 0; r < 3; ++r) y2[r] = beta * UC[r] + oq * (gL<G>(Z[r]) + gR<G>(Z[r])) + oh * Z[r];
+    const cx<T> d1lo = y1 - gL<G>(y1);
+    const cx<T> d1hi = gR<G>(d1lo);
     const cx<T> d2lo = y2[1] - y2[0], d2hi = y2[2] - y2[1];
     cx<T> acc, F3n, dv;
     if (K == 0) {
@@ -366,32 +389,32 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
       // four cells around the edge (pairs along x_1 first)
       T MXb[3], MXn1;
 #pragma unroll
-      for (int r = 0; r < 3; ++r) MXb[r] = hf * (fromL(MC[r]) + MC[r]);
-      MXn1 = hf * (fromL(mun[1]) + mun[1]);
-      acc = fromL(MC[1]) * d1lo - MC[1] * d1hi;
+      for (int r = 0; r < 3; ++r) MXb[r] = hf * (gL<G>(MC[r]) + MC[r]);
+      MXn1 = hf * (gL<G>(mun[1]) + mun[1]);
+      acc = gL<G>(MC[1]) * d1lo - MC[1] * d1hi;
       acc += (hf * (MXb[0] + MXb[1])) * d2lo - (hf * (MXb[1] + MXb[2])) * d2hi;
       F3n = (hf * (MXb[1] + MXn1)) * (Y3n - Y3b);
       dv = d1hi;
     } else if (K == 1) {
       const T MYb = hf * (MC[0] + MC[1]), MYn = hf * (mun[0] + mun[1]);
       acc = MC[0] * d2lo - MC[1] * d2hi;
-      acc += (hf * (fromL(MYb) + MYb)) * d1lo - (hf * (MYb + fromR(MYb))) * d1hi;
+      acc += (hf * (gL<G>(MYb) + MYb)) * d1lo - (hf * (MYb + gR<G>(MYb))) * d1hi;
       F3n = (hf * (MYb + MYn)) * (Y3n - Y3b);
       dv = d2hi;
     } else {
       const T MZm = hf * (MO[0] + MC[0]), MZc = hf * (MO[1] + MC[1]), MZp = hf * (MO[2] + MC[2]);
-      acc = (hf * (fromL(MZc) + MZc)) * d1lo - (hf * (MZc + fromR(MZc))) * d1hi;
+      acc = (hf * (gL<G>(MZc) + MZc)) * d1lo - (hf * (MZc + gR<G>(MZc))) * d1hi;
       acc += (hf * (MZm + MZc)) * d2lo - (hf * (MZc + MZp)) * d2hi;
       F3n = MC[1] * (Y3n - Y3b);
       dv = Y3n - Y3b;
     }
     acc = C.ih2 * (acc + F3 - F3n);
     // spread mass with the attenuation of the output face
-    const cx<T> nb = fromL(WC) + fromR(WC) + Wmp + WO + Wn;
+    const cx<T> nb = gL<G>(WC) + gR<G>(WC) + Wmp + WO + Wn;
     const cx<T> sm = beta * WC + C.cn * nb;
     acc -= mk(C.omega2, -C.omega2 * (C.gf + a3)) * sm;
     // coupling with p: the cell above the face minus the cell below
-    if (K == 0) acc += C.ih * (PC - fromL(PC));
+    if (K == 0) acc += C.ih * (PC - gL<G>(PC));
     if (K == 1) acc += C.ih * (PC - Pbm);
     if (K == 2) acc += C.ih * (PC - PO);
     const bool emit = !RR && C.outlane && t >= C.z0;
@@ -776,25 +799,37 @@ k_apply3d_w3_adj(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __res
   else w3_march_adj<2, T, RESID>(C, DV);
 }
 
+// Tiles per (x_3 chunk, rhs): nfull 62-wide segments of every row (x_1
+// fastest), then nrem tiles of RG_ROWS rows each for the last n_1 - 62 nfull
+// (<= RG_OUT) cells of a row.
 template <typename T, typename TI, bool RESID>
 __global__ void __launch_bounds__(WV_LANES * 3)
 k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
-             int tiles_x, int nzc, int zc, int ntiles, int per_xcd) {
+             int nfull, int nrem, int nzc, int zc, int ntiles, int per_xcd) {
   __shared__ cx<T> DV[2][3][WV_LANES];
   const int bid = blockIdx.x;
   const int tile = (bid & 7) * per_xcd + (bid >> 3);
   if (tile >= ntiles) return;  // whole workgroup
+  const int per_chunk = nfull * L.n[1] + nrem;
   int rest = tile;
-  const int tx = rest % tiles_x; rest /= tiles_x;
-  const int c2 = rest % L.n[1]; rest /= L.n[1];
+  const int in = rest % per_chunk; rest /= per_chunk;
   const int tz = rest % nzc; rest /= nzc;
   const int s = rest;
   W3Ctx<T> C;
   const int k = threadIdx.y;
-  w3_setup<T, TI, RESID>(C, L, x, b, y, tx * WV_OUT - 1, k, c2, tz, zc, s);
-  if (k == 0) w3_march<0, T, TI, RESID>(C, DV);
-  else if (k == 1) w3_march<1, T, TI, RESID>(C, DV);
-  else w3_march<2, T, TI, RESID>(C, DV);
+  if (in < nfull * L.n[1]) {
+    const int tx = in % nfull, c2 = in / nfull;
+    w3_setup<T, TI, RESID>(C, L, x, b, y, tx * WV_OUT - 1, k, c2, tz, zc, s);
+    if (k == 0) w3_march<0, T, TI, RESID>(C, DV);
+    else if (k == 1) w3_march<1, T, TI, RESID>(C, DV);
+    else w3_march<2, T, TI, RESID>(C, DV);
+  } else {
+    const int c2 = (in - nfull * L.n[1]) * RG_ROWS + (int)(threadIdx.x / RG_LANES);
+    w3_setup<T, TI, RESID, RG_LANES>(C, L, x, b, y, nfull * WV_OUT - 1, k, c2, tz, zc, s);
+    if (k == 0) w3_march<0, T, TI, RESID, false, RG_LANES>(C, DV);
+    else if (k == 1) w3_march<1, T, TI, RESID, false, RG_LANES>(C, DV);
+    else w3_march<2, T, TI, RESID, false, RG_LANES>(C, DV);
+  }
 }
 
 // Residual + restriction, rc = R (b - H_s x) (ADJ: H_s^H): a workgroup of
@@ -854,10 +889,10 @@ k_restrict_resid3d_w3(LevelArgs<T> L, LevelArgs<T> Lc, const cx<T>* __restrict__
 // x_3 chunk length: zc < 0 asks for exactly -zc planes (the autotuner's
 // candidates); otherwise zc (default 32) shortened so that at least ~8192
 // workgroups are in flight on small grids
-static int w3_chunk(const int* n, int tiles_x, int nrhs, int zc) {
+static int w3_chunk(const int* n, int64_t cols_per_rhs, int nrhs, int zc) {
   if (zc < 0) return -zc < n[2] ? -zc : n[2];
   if (zc == 0) zc = 32;
-  const int64_t cols = (int64_t)tiles_x * n[1] * nrhs;
+  const int64_t cols = cols_per_rhs * nrhs;
   const int64_t want = (int64_t)n[2] * cols / 8192;
   if (want < zc) zc = (int)(want < 4 ? 4 : want);
   if (zc > n[2]) zc = n[2];
@@ -867,21 +902,27 @@ static int w3_chunk(const int* n, int tiles_x, int nrhs, int zc) {
 template <typename T, typename TI>
 int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
                       hipStream_t st) {
-  const int tiles_x = (L.n[0] + WV_OUT - 1) / WV_OUT;
   if (L.fs * (int64_t)sizeof(cx<T>) > (int64_t)0x7fffffff) return (int)hipErrorInvalidValue;
-  zc = w3_chunk(L.n, tiles_x, nrhs, zc);
+  // full 62-wide segments; a remainder of at most RG_OUT cells goes to
+  // 16-lane row groups, a longer one to one more full segment
+  int nfull = L.n[0] / WV_OUT, nrem = 0;
+  const int rem = L.n[0] - nfull * WV_OUT;
+  if (rem > RG_OUT) ++nfull;
+  else if (rem > 0) nrem = (L.n[1] + RG_ROWS - 1) / RG_ROWS;
+  const int64_t per_chunk = (int64_t)nfull * L.n[1] + nrem;
+  zc = w3_chunk(L.n, per_chunk, nrhs, zc);
   const int nzc = (L.n[2] + zc - 1) / zc;
-  const int64_t ntiles64 = (int64_t)tiles_x * L.n[1] * nzc * nrhs;
+  const int64_t ntiles64 = per_chunk * nzc * nrhs;
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
   const int ntiles = (int)ntiles64;
   const int per_xcd = (ntiles + 7) / 8;
   dim3 blk(WV_LANES, 3), grd(8 * per_xcd);
   if (b)
     ELH_LAUNCH((k_apply3d_w3<T, TI, true>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)b,
-                       (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
+                       (cx<T>*)y, nfull, nrem, nzc, zc, ntiles, per_xcd);
   else
     ELH_LAUNCH((k_apply3d_w3<T, TI, false>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)nullptr,
-                       (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
+                       (cx<T>*)y, nfull, nrem, nzc, zc, ntiles, per_xcd);
   return (int)hipGetLastError();
 }
 
@@ -890,7 +931,7 @@ int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, v
                           hipStream_t st) {
   const int tiles_x = (L.n[0] + WV_OUT - 1) / WV_OUT;
   if (L.fs * (int64_t)sizeof(cx<T>) > (int64_t)0x7fffffff) return (int)hipErrorInvalidValue;
-  zc = w3_chunk(L.n, tiles_x, nrhs, zc);
+  zc = w3_chunk(L.n, (int64_t)tiles_x * L.n[1], nrhs, zc);
   const int nzc = (L.n[2] + zc - 1) / zc;
   const int64_t ntiles64 = (int64_t)tiles_x * L.n[1] * nzc * nrhs;
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
@@ -915,7 +956,7 @@ int launch_restrict_resid3d_w3(const LevelArgs<T>& F, const LevelArgs<T>& Cl, bo
   const int tiles_x = (F.n[0] + (WV_OUT - 2) - 1) / (WV_OUT - 2);
   // chunk in coarse planes (same heuristic, counted on the coarse rows)
   const int nc[3] = {Cl.n[0], Cl.n[1], Cl.n[2]};
-  zc = w3_chunk(nc, tiles_x, nrhs, zc);
+  zc = w3_chunk(nc, (int64_t)tiles_x * Cl.n[1], nrhs, zc);
   const int nzc = (Cl.n[2] + zc - 1) / zc;
   const int64_t ntiles64 = (int64_t)tiles_x * Cl.n[1] * nzc * nrhs;
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;

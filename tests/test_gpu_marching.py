@@ -23,8 +23,9 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 3e-5
-# (n_3, n_2, n_1): n_1 = 70 and 130 give two and three x_1 segments of 62
-# lanes (the last one ragged); n_3 = 10, 17 and 18 give ragged x_3 chunks
+# (n_3, n_2, n_1): n_1 = 70 and 130 give one and two x_1 segments of 62 lanes and a remainder
+# of 8 and 6 cells in 16-lane row groups (n_2 = 9 leaves three rows of the last group empty);
+# n_3 = 10, 17 and 18 give ragged x_3 chunks
 SHAPES = [(10, 12, 70), (17, 9, 130)]
 EVEN_SHAPES = [(10, 12, 70), (18, 10, 130)]  # two-level hierarchies
 
