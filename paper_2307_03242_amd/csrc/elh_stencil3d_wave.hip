@@ -799,9 +799,11 @@ k_apply3d_w3_adj(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __res
   else w3_march_adj<2, T, RESID>(C, DV);
 }
 
-// Tiles per (x_3 chunk, rhs): nfull 62-wide segments of every row (x_1
-// fastest), then nrem tiles of RG_ROWS rows each for the last n_1 - 62 nfull
-// (<= RG_OUT) cells of a row.
+// Tiles per (x_3 chunk, rhs), in groups of RG_ROWS rows: the nfull 62-wide
+// segments of each row of the group (x_1 fastest), then, when nrem is set,
+// one tile for the last n_1 - 62 nfull (<= RG_OUT) cells of the group's rows,
+// right after the segments whose cache lines it shares.  Tiles of rows beyond
+// n_2 (last group) do nothing.
 template <typename T, typename TI, bool RESID>
 __global__ void __launch_bounds__(WV_LANES * 3)
 k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
@@ -810,21 +812,24 @@ k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restri
   const int bid = blockIdx.x;
   const int tile = (bid & 7) * per_xcd + (bid >> 3);
   if (tile >= ntiles) return;  // whole workgroup
-  const int per_chunk = nfull * L.n[1] + nrem;
+  const int gs = RG_ROWS * nfull + nrem;  // tiles per group of rows
+  const int per_chunk = (L.n[1] + RG_ROWS - 1) / RG_ROWS * gs;
   int rest = tile;
   const int in = rest % per_chunk; rest /= per_chunk;
   const int tz = rest % nzc; rest /= nzc;
   const int s = rest;
+  const int g = in / gs, j = in - g * gs;
   W3Ctx<T> C;
   const int k = threadIdx.y;
-  if (in < nfull * L.n[1]) {
-    const int tx = in % nfull, c2 = in / nfull;
+  if (j < RG_ROWS * nfull) {
+    const int tx = j % nfull, c2 = g * RG_ROWS + j / nfull;
+    if (c2 >= L.n[1]) return;  // whole workgroup
     w3_setup<T, TI, RESID>(C, L, x, b, y, tx * WV_OUT - 1, k, c2, tz, zc, s);
     if (k == 0) w3_march<0, T, TI, RESID>(C, DV);
     else if (k == 1) w3_march<1, T, TI, RESID>(C, DV);
     else w3_march<2, T, TI, RESID>(C, DV);
   } else {
-    const int c2 = (in - nfull * L.n[1]) * RG_ROWS + (int)(threadIdx.x / RG_LANES);
+    const int c2 = g * RG_ROWS + (int)(threadIdx.x / RG_LANES);
     w3_setup<T, TI, RESID, RG_LANES>(C, L, x, b, y, nfull * WV_OUT - 1, k, c2, tz, zc, s);
     if (k == 0) w3_march<0, T, TI, RESID, false, RG_LANES>(C, DV);
     else if (k == 1) w3_march<1, T, TI, RESID, false, RG_LANES>(C, DV);
@@ -908,8 +913,8 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
   int nfull = L.n[0] / WV_OUT, nrem = 0;
   const int rem = L.n[0] - nfull * WV_OUT;
   if (rem > RG_OUT) ++nfull;
-  else if (rem > 0) nrem = (L.n[1] + RG_ROWS - 1) / RG_ROWS;
-  const int64_t per_chunk = (int64_t)nfull * L.n[1] + nrem;
+  else if (rem > 0) nrem = 1;
+  const int64_t per_chunk = (int64_t)(L.n[1] + RG_ROWS - 1) / RG_ROWS * (RG_ROWS * nfull + nrem);
   zc = w3_chunk(L.n, per_chunk, nrhs, zc);
   const int nzc = (L.n[2] + zc - 1) / zc;
   const int64_t ntiles64 = per_chunk * nzc * nrhs;
