@@ -13,8 +13,9 @@
 //  * neighbours along x_1 are other lanes of the same wavefront, read with
 //    DPP wavefront shifts;
 //  * neighbours along x_2 (rows c-1, c+1; rho also at c-2) are loaded
-//    directly; the workgroups of neighbouring rows run on the same XCD
-//    (XCD-aware tile order), so these loads hit L2;
+//    directly; the segments of four neighbouring rows run on the same XCD
+//    (tile order below), so these loads hit its L2, while the eight XCDs
+//    work through the same x_3 chunk at once;
 //  * along x_3 each wavefront keeps rolling register windows of its one
 //    component (u at rows c-1..c+1, planes t-1 and t; the spread field Y_3;
 //    the carried x_3 flux; the rho-weighted u of the spread mass; mu; p);
@@ -38,6 +39,18 @@ constexpr int WV_OUT = WV_LANES - 2;   // outputs per wave along x_1
 constexpr int RG_LANES = 16;
 constexpr int RG_OUT = RG_LANES - 2;
 constexpr int RG_ROWS = WV_LANES / RG_LANES;
+
+// Tile order.  Workgroups go to the eight XCDs in turn (block b runs on XCD
+// b mod 8), each with its own L2.  Consecutive groups of S tiles (the
+// segments of a few neighbouring rows of one x_3 chunk) are dealt to the
+// XCDs in turn, so the rows of a group share one L2 while all eight XCDs
+// work through the same x_3 chunk at the same time.  The grid is padded to
+// a multiple of 8 S; tiles at or beyond the count do nothing.
+__device__ __forceinline__ int w3_tile(int S) {
+  const int bid = blockIdx.x, slot = bid >> 3;
+  return ((slot / S) * 8 + (bid & 7)) * S + slot % S;
+}
+static unsigned w3_grid(int64_t ntiles, int S) { return (unsigned)(8 * S * ((ntiles + 8 * S - 1) / (8 * S))); }
 
 // DPP wavefront shifts: FROM_LEFT gives lane i the value of lane i-1,
 // FROM_RIGHT the value of lane i+1 (zero where that lane does not exist).
@@ -781,10 +794,9 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
 template <typename T, bool RESID>
 __global__ void __launch_bounds__(WV_LANES * 3)
 k_apply3d_w3_adj(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
-                 int tiles_x, int nzc, int zc, int ntiles, int per_xcd) {
+                 int tiles_x, int nzc, int zc, int ntiles) {
   __shared__ cx<T> DV[2][3][WV_LANES];
-  const int bid = blockIdx.x;
-  const int tile = (bid & 7) * per_xcd + (bid >> 3);
+  const int tile = w3_tile(RG_ROWS * tiles_x);
   if (tile >= ntiles) return;  // whole workgroup
   int rest = tile;
   const int tx = rest % tiles_x; rest /= tiles_x;
@@ -807,12 +819,11 @@ k_apply3d_w3_adj(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __res
 template <typename T, typename TI, bool RESID>
 __global__ void __launch_bounds__(WV_LANES * 3)
 k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
-             int nfull, int nrem, int nzc, int zc, int ntiles, int per_xcd) {
+             int nfull, int nrem, int nzc, int zc, int ntiles) {
   __shared__ cx<T> DV[2][3][WV_LANES];
-  const int bid = blockIdx.x;
-  const int tile = (bid & 7) * per_xcd + (bid >> 3);
-  if (tile >= ntiles) return;  // whole workgroup
   const int gs = RG_ROWS * nfull + nrem;  // tiles per group of rows
+  const int tile = w3_tile(gs);
+  if (tile >= ntiles) return;  // whole workgroup
   const int per_chunk = (L.n[1] + RG_ROWS - 1) / RG_ROWS * gs;
   int rest = tile;
   const int in = rest % per_chunk; rest /= per_chunk;
@@ -848,11 +859,10 @@ k_apply3d_w3(LevelArgs<T> L, const cx<TI>* __restrict__ x, const cx<T>* __restri
 template <typename T, bool ADJ>
 __global__ void __launch_bounds__(WV_LANES * 7)
 k_restrict_resid3d_w3(LevelArgs<T> L, LevelArgs<T> Lc, const cx<T>* __restrict__ x, const cx<T>* __restrict__ b,
-                      cx<T>* __restrict__ yc, int tiles_x, int nzc, int zc, int ntiles, int per_xcd) {
+                      cx<T>* __restrict__ yc, int tiles_x, int nzc, int zc, int ntiles) {
   __shared__ cx<T> DV[3][2][3][WV_LANES];  // per fine row (2J, 2J+1; unused third for wave 6)
   __shared__ cx<T> RZ[2][5][WV_LANES];
-  const int bid = blockIdx.x;
-  const int tile = (bid & 7) * per_xcd + (bid >> 3);
+  const int tile = w3_tile(2 * tiles_x);  // groups of two coarse (four fine) rows
   if (tile >= ntiles) return;  // whole workgroup
   int rest = tile;
   const int tx = rest % tiles_x; rest /= tiles_x;
@@ -920,14 +930,13 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
   const int64_t ntiles64 = per_chunk * nzc * nrhs;
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
   const int ntiles = (int)ntiles64;
-  const int per_xcd = (ntiles + 7) / 8;
-  dim3 blk(WV_LANES, 3), grd(8 * per_xcd);
+  dim3 blk(WV_LANES, 3), grd(w3_grid(ntiles, RG_ROWS * nfull + nrem));
   if (b)
     ELH_LAUNCH((k_apply3d_w3<T, TI, true>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)b,
-                       (cx<T>*)y, nfull, nrem, nzc, zc, ntiles, per_xcd);
+                       (cx<T>*)y, nfull, nrem, nzc, zc, ntiles);
   else
     ELH_LAUNCH((k_apply3d_w3<T, TI, false>), grd, blk, 0, st, L, (const cx<TI>*)x, (const cx<T>*)nullptr,
-                       (cx<T>*)y, nfull, nrem, nzc, zc, ntiles, per_xcd);
+                       (cx<T>*)y, nfull, nrem, nzc, zc, ntiles);
   return (int)hipGetLastError();
 }
 
@@ -941,14 +950,13 @@ int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, v
   const int64_t ntiles64 = (int64_t)tiles_x * L.n[1] * nzc * nrhs;
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
   const int ntiles = (int)ntiles64;
-  const int per_xcd = (ntiles + 7) / 8;
-  dim3 blk(WV_LANES, 3), grd(8 * per_xcd);
+  dim3 blk(WV_LANES, 3), grd(w3_grid(ntiles, RG_ROWS * tiles_x));
   if (b)
     ELH_LAUNCH((k_apply3d_w3_adj<T, true>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b,
-                       (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
+                       (cx<T>*)y, tiles_x, nzc, zc, ntiles);
   else
     ELH_LAUNCH((k_apply3d_w3_adj<T, false>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)nullptr,
-                       (cx<T>*)y, tiles_x, nzc, zc, ntiles, per_xcd);
+                       (cx<T>*)y, tiles_x, nzc, zc, ntiles);
   return (int)hipGetLastError();
 }
 template <typename T>
@@ -966,14 +974,13 @@ int launch_restrict_resid3d_w3(const LevelArgs<T>& F, const LevelArgs<T>& Cl, bo
   const int64_t ntiles64 = (int64_t)tiles_x * Cl.n[1] * nzc * nrhs;
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
   const int ntiles = (int)ntiles64;
-  const int per_xcd = (ntiles + 7) / 8;
-  dim3 blk(WV_LANES, 7), grd(8 * per_xcd);
+  dim3 blk(WV_LANES, 7), grd(w3_grid(ntiles, 2 * tiles_x));
   if (adj)
     ELH_LAUNCH((k_restrict_resid3d_w3<T, true>), grd, blk, 0, st, F, Cl, (const cx<T>*)x, (const cx<T>*)b,
-                       (cx<T>*)rc, tiles_x, nzc, zc, ntiles, per_xcd);
+                       (cx<T>*)rc, tiles_x, nzc, zc, ntiles);
   else
     ELH_LAUNCH((k_restrict_resid3d_w3<T, false>), grd, blk, 0, st, F, Cl, (const cx<T>*)x,
-                       (const cx<T>*)b, (cx<T>*)rc, tiles_x, nzc, zc, ntiles, per_xcd);
+                       (const cx<T>*)b, (cx<T>*)rc, tiles_x, nzc, zc, ntiles);
   return (int)hipGetLastError();
 }
 template int launch_restrict_resid3d_w3<double>(const LevelArgs<double>&, const LevelArgs<double>&, bool,
