@@ -508,8 +508,9 @@ __device__ __forceinline__ void w3_march(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LA
 // attenuated u of the mass at (c, t-1), (c, t); the partial spreads of p.
 // RR: restriction mode as in w3_march (one step per plane here, so the
 // plane parity is a run-time value).
-template <int K, typename T, bool RESID, bool RR = false>
+template <int K, typename T, bool RESID, bool RR = false, int G = WV_LANES>
 __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][WV_LANES]) {
+  static_assert(G == WV_LANES || !RR, "the fused restriction marches whole wavefronts");
   constexpr int CB = (int)sizeof(cx<T>), RBY = (int)sizeof(T);
   const T q = T(0.25), hf = T(0.5);
   const T beta = C.beta;
@@ -553,7 +554,7 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
     return C.has_abl ? C.ablz[(K == 2 ? n3 : 0) + min(max(z, 0), n3 - 1)] : T(0);
   };
   auto att = [&](T g, cx<T> u) { return mk(u.re - g * u.im, u.im + g * u.re); };  // (1 + i g) u
-  auto A1 = [&](cx<T> v) { return q * (fromL(v) + fromR(v)) + hf * v; };
+  auto A1 = [&](cx<T> v) { return q * (gL<G>(v) + gR<G>(v)) + hf * v; };
 
   // loads in flight for the next plane
   cx<T> nu[3], np[3];
@@ -664,7 +665,7 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
       for (int r = 0; r < 3; ++r) {
         MYn[r] = hf * (mun[r] + mun[r + 1]);
         MYb[r] = hf * (mub[r] + mub[r + 1]);
-        mu1[r] = hf * (fromL(MYn[r]) + MYn[r]);
+        mu1[r] = hf * (gL<G>(MYn[r]) + MYn[r]);
         mu3[r] = hf * (MYb[r] + MYn[r]);
       }
       mu2l = mun[1];  // cell mu of rows c-1 and c (flux along x_2 of u_2)
@@ -674,7 +675,7 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         MZn[r] = hf * (mub[r + 1] + mun[r + 1]);
-        mu1[r] = hf * (fromL(MZn[r]) + MZn[r]);
+        mu1[r] = hf * (gL<G>(MZn[r]) + MZn[r]);
         mu3[r] = mub[r + 1];  // cell mu of plane t (flux along x_3 of u_3)
       }
       mu2l = hf * (MZn[0] + MZn[1]);
@@ -683,10 +684,10 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
     // flux along x_1 at plane t+1 (lane x: cell x for u_1, edge x otherwise)
     cx<T> G1n[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) G1n[r] = mu1[r] * (K == 0 ? fromR(Un[r]) - Un[r] : Un[r] - fromL(Un[r]));
+    for (int r = 0; r < 3; ++r) G1n[r] = mu1[r] * (K == 0 ? gR<G>(Un[r]) - Un[r] : Un[r] - gL<G>(Un[r]));
     const cx<T> X1n = q * (G1n[0] + G1n[2]) + hf * G1n[1];
     const cx<T> SG1 = beta * G1b + oq * (X1a + X1n) + oh * X1b;
-    cx<T> acc = K == 0 ? fromL(SG1) - SG1 : SG1 - fromR(SG1);
+    cx<T> acc = K == 0 ? gL<G>(SG1) - SG1 : SG1 - gR<G>(SG1);
     // flux along x_2 at the lower / upper flux row, plane t+1
     const cx<T> G2ln = mu2l * (Un[1] - Un[0]), G2hn = mu2h * (Un[2] - Un[1]);
     const cx<T> Q2ln = A1(G2ln), Q2hn = A1(G2hn);
@@ -698,16 +699,16 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
 #pragma unroll
     for (int r = 0; r < 3; ++r) G3[r] = mu3[r] * (Un[r] - UC[r]);
     const cx<T> V3 = q * (G3[0] + G3[2]) + hf * G3[1];
-    const cx<T> SG3n = beta * G3[1] + oq * (fromL(V3) + fromR(V3)) + oh * V3;
+    const cx<T> SG3n = beta * G3[1] + oq * (gL<G>(V3) + gR<G>(V3)) + oh * V3;
     acc += SG3 - SG3n;
     acc = C.ih2 * acc;
     // adjoint spread mass: rho_f of the output face times the spread of
     // (1 + i gamma~) u over the seven points
     const cx<T> Wn = att(gxy[1] + a3n, Un[1]);
-    const cx<T> nb = fromL(Wb) + fromR(Wb) + att(gxy[0] + a3b, UC[0]) + att(gxy[2] + a3b, UC[2]) + Wa + Wn;
+    const cx<T> nb = gL<G>(Wb) + gR<G>(Wb) + att(gxy[0] + a3b, UC[0]) + att(gxy[2] + a3b, UC[2]) + Wa + Wn;
     const cx<T> sm = beta * Wb + C.cn * nb;
     T rfP;
-    if (K == 0) rfP = hf * (fromL(rhob1) + rhob1);
+    if (K == 0) rfP = hf * (gL<G>(rhob1) + rhob1);
     else if (K == 1) rfP = hf * (rhob0 + rhob1);
     else rfP = hf * (rhoa + rhob1);
     acc -= (C.omega2 * rfP) * sm;
@@ -716,8 +717,8 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
     if (K == 0) {
       const cx<T> A2n = q * (Pn[0] + Pn[2]) + hf * Pn[1];
       const cx<T> SP = beta * Pc0 + oq * (Pa0 + A2n) + oh * Pb0;
-      acc += C.ih * (fromL(SP) - SP);
-      dv = UC[1] - fromR(UC[1]);
+      acc += C.ih * (gL<G>(SP) - SP);
+      dv = UC[1] - gR<G>(UC[1]);
       Pa0 = Pb0; Pb0 = A2n; Pc1 = Pc0; Pc0 = Pn[1];  // Pc1: p(c, t) for the p row
     } else if (K == 1) {
       const cx<T> A1m = A1(Pn[0]), A1c = A1(Pn[1]);
@@ -728,7 +729,7 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
       Pa0 = Pb0; Pb0 = A1m; Pa1 = Pb1; Pb1 = A1c; Pc0 = Pn[0]; Pc1 = Pn[1];
     } else {
       const cx<T> V = q * (Pn[0] + Pn[2]) + hf * Pn[1];
-      const cx<T> SPn = beta * Pn[1] + oq * (fromL(V) + fromR(V)) + oh * V;
+      const cx<T> SPn = beta * Pn[1] + oq * (gL<G>(V) + gR<G>(V)) + oh * V;
       acc += C.ih * (Pa0 - Pb0);
       dv = UC[1] - Un[1];
       Pa0 = Pb0; Pb0 = SPn;
@@ -794,21 +795,34 @@ __device__ __forceinline__ void w3_march_adj(const W3Ctx<T>& C, cx<T> (*DV)[3][W
 template <typename T, bool RESID>
 __global__ void __launch_bounds__(WV_LANES * 3)
 k_apply3d_w3_adj(LevelArgs<T> L, const cx<T>* __restrict__ x, const cx<T>* __restrict__ b, cx<T>* __restrict__ y,
-                 int tiles_x, int nzc, int zc, int ntiles) {
+                 int nfull, int nrem, int nzc, int zc, int ntiles) {
+  // tiles as in k_apply3d_w3
   __shared__ cx<T> DV[2][3][WV_LANES];
-  const int tile = w3_tile(RG_ROWS * tiles_x);
+  const int gs = RG_ROWS * nfull + nrem;
+  const int tile = w3_tile(gs);
   if (tile >= ntiles) return;  // whole workgroup
+  const int per_chunk = (L.n[1] + RG_ROWS - 1) / RG_ROWS * gs;
   int rest = tile;
-  const int tx = rest % tiles_x; rest /= tiles_x;
-  const int c2 = rest % L.n[1]; rest /= L.n[1];
+  const int in = rest % per_chunk; rest /= per_chunk;
   const int tz = rest % nzc; rest /= nzc;
   const int s = rest;
+  const int g = in / gs, j = in - g * gs;
   W3Ctx<T> C;
   const int k = threadIdx.y;
-  w3_setup<T, T, RESID>(C, L, x, b, y, tx * WV_OUT - 1, k, c2, tz, zc, s);
-  if (k == 0) w3_march_adj<0, T, RESID>(C, DV);
-  else if (k == 1) w3_march_adj<1, T, RESID>(C, DV);
-  else w3_march_adj<2, T, RESID>(C, DV);
+  if (j < RG_ROWS * nfull) {
+    const int tx = j % nfull, c2 = g * RG_ROWS + j / nfull;
+    if (c2 >= L.n[1]) return;  // whole workgroup
+    w3_setup<T, T, RESID>(C, L, x, b, y, tx * WV_OUT - 1, k, c2, tz, zc, s);
+    if (k == 0) w3_march_adj<0, T, RESID>(C, DV);
+    else if (k == 1) w3_march_adj<1, T, RESID>(C, DV);
+    else w3_march_adj<2, T, RESID>(C, DV);
+  } else {
+    const int c2 = g * RG_ROWS + (int)(threadIdx.x / RG_LANES);
+    w3_setup<T, T, RESID, RG_LANES>(C, L, x, b, y, nfull * WV_OUT - 1, k, c2, tz, zc, s);
+    if (k == 0) w3_march_adj<0, T, RESID, false, RG_LANES>(C, DV);
+    else if (k == 1) w3_march_adj<1, T, RESID, false, RG_LANES>(C, DV);
+    else w3_march_adj<2, T, RESID, false, RG_LANES>(C, DV);
+  }
 }
 
 // Tiles per (x_3 chunk, rhs), in groups of RG_ROWS rows: the nfull 62-wide
@@ -943,20 +957,24 @@ int launch_apply3d_w3(const LevelArgs<T>& L, const void* x, const void* b, void*
 template <typename T>
 int launch_apply3d_w3_adj(const LevelArgs<T>& L, const void* x, const void* b, void* y, int nrhs, int zc,
                           hipStream_t st) {
-  const int tiles_x = (L.n[0] + WV_OUT - 1) / WV_OUT;
   if (L.fs * (int64_t)sizeof(cx<T>) > (int64_t)0x7fffffff) return (int)hipErrorInvalidValue;
-  zc = w3_chunk(L.n, (int64_t)tiles_x * L.n[1], nrhs, zc);
+  int nfull = L.n[0] / WV_OUT, nrem = 0;  // as in launch_apply3d_w3
+  const int rem = L.n[0] - nfull * WV_OUT;
+  if (rem > RG_OUT) ++nfull;
+  else if (rem > 0) nrem = 1;
+  const int64_t per_chunk = (int64_t)(L.n[1] + RG_ROWS - 1) / RG_ROWS * (RG_ROWS * nfull + nrem);
+  zc = w3_chunk(L.n, per_chunk, nrhs, zc);
   const int nzc = (L.n[2] + zc - 1) / zc;
-  const int64_t ntiles64 = (int64_t)tiles_x * L.n[1] * nzc * nrhs;
+  const int64_t ntiles64 = per_chunk * nzc * nrhs;
   if (ntiles64 > (1ll << 30)) return (int)hipErrorInvalidValue;
   const int ntiles = (int)ntiles64;
-  dim3 blk(WV_LANES, 3), grd(w3_grid(ntiles, RG_ROWS * tiles_x));
+  dim3 blk(WV_LANES, 3), grd(w3_grid(ntiles, RG_ROWS * nfull + nrem));
   if (b)
     ELH_LAUNCH((k_apply3d_w3_adj<T, true>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)b,
-                       (cx<T>*)y, tiles_x, nzc, zc, ntiles);
+                       (cx<T>*)y, nfull, nrem, nzc, zc, ntiles);
   else
     ELH_LAUNCH((k_apply3d_w3_adj<T, false>), grd, blk, 0, st, L, (const cx<T>*)x, (const cx<T>*)nullptr,
-                       (cx<T>*)y, tiles_x, nzc, zc, ntiles);
+                       (cx<T>*)y, nfull, nrem, nzc, zc, ntiles);
   return (int)hipGetLastError();
 }
 template <typename T>
