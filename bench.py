@@ -33,11 +33,11 @@ RESID_BYTES_F32 = 108      # residual b - H_s x in complex64: x, b, y (32 B each
 # HBM bytes per launch of the float32 residual at 256^3 from the rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes over `bench.py --pmc-target`
 # (profiles/stencil_256cubed_counters.md; FETCH_SIZE x2.0, WRITE_SIZE x1.0):
-# 1.810 GB read + 0.563 GB written, measured on the kernel source whose
+# 1.822 GB read + 0.563 GB written, measured on the kernel source whose
 # SHA-256 prefix is RESID_TRAFFIC_SOURCE.  When the source changes the
 # figure is not reported (null) until the passes are repeated.
-RESID_TRAFFIC_BYTES = 2.373e9
-RESID_TRAFFIC_SOURCE = "54ef3f73bb0e52c0"
+RESID_TRAFFIC_BYTES = 2.385e9
+RESID_TRAFFIC_SOURCE = "0668f9b40eca824f"
 STENCIL_SOURCE = os.path.join(ROOT, "paper_2307_03242_amd", "csrc", "elh_stencil3d_wave.hip")
 
 
