@@ -638,9 +638,14 @@ __global__ void __launch_bounds__(256) k_prolong3(LevelArgs<T> F, LevelArgs<T> C
           ao += (wp * w12) * eP;
         }
       }
-    cx<T>* xf = xs + (int64_t)f * F.fs + cell;
-    if (f != 0 || I != 0) xf[0] += ae;  // fine face 0 along x_1 is not an unknown
-    xf[1] += ao;
+    // cells 2I and 2I+1 are adjacent and the pair is aligned to its size
+    // (even cell index, even n_1): one wide load and one wide store
+    struct alignas(2 * sizeof(cx<T>)) Pair { cx<T> a, b; };
+    Pair* xf = reinterpret_cast<Pair*>(xs + (int64_t)f * F.fs + cell);
+    Pair v = *xf;
+    if (f != 0 || I != 0) v.a += ae;  // fine face 0 along x_1 is not an unknown
+    v.b += ao;
+    *xf = v;
   }
 }
 
