@@ -685,7 +685,9 @@ template <typename T>
 int launch_prolong_add(const LevelArgs<T>& F, const LevelArgs<T>& C, int dim, const void* e, void* x, int nrhs,
                        hipStream_t st) {
   dim3 blk(256), grd((unsigned)((F.fs + 255) / 256), nrhs);
-  if (dim == 3 && F.fs <= 0x7fffffffll && (F.n[0] & 1) == 0 && F.n[0] == 2 * C.n[0])
+  // the pair kernel updates two adjacent fine cells with one aligned access
+  const bool pair_aligned = reinterpret_cast<uintptr_t>(x) % (2 * sizeof(cx<T>)) == 0;
+  if (dim == 3 && F.fs <= 0x7fffffffll && (F.n[0] & 1) == 0 && F.n[0] == 2 * C.n[0] && pair_aligned)
     ELH_LAUNCH((k_prolong3<T>), dim3((unsigned)((F.fs / 2 + 255) / 256), nrhs), blk, 0, st, F, C,
                        (const cx<T>*)e, (cx<T>*)x, nrhs);
   else if (dim == 3)

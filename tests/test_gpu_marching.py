@@ -107,6 +107,26 @@ def test_marching_prolong_add(shape):
     assert _maxrel(out, ref) <= 1e-14
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_prolong_add_unaligned_output_matches_aligned(dtype):
+    """x one element past a pair boundary (a view into a larger buffer): the
+    launcher takes the per-cell kernel instead of the pair kernel's wide
+    accesses, with the same result"""
+    shape = EVEN_SHAPES[0]
+    prob, lv = _setup(shape, levels=2)
+    lvc = C.coarsen_level(lv)
+    x = _dev(random_field(shape, 41, nrhs=1), dtype)
+    e = _dev(random_field(lvc.np_shape, 42, nrhs=1), dtype)
+    aligned = prob.prolong_add(e, x.clone())
+    big = torch.zeros(x.numel() + 1, dtype=dtype, device="cuda")
+    xu = big[1:].view(x.shape)
+    xu.copy_(x)
+    assert xu.data_ptr() % (2 * x.element_size()) != 0
+    prob.prolong_add(e, xu)
+    tol = 1e-6 if dtype == torch.complex64 else 1e-14
+    assert _maxrel(_host(xu), _host(aligned)) <= tol
+
+
 @pytest.mark.parametrize("shape", EVEN_SHAPES)
 def test_marching_vcycle_and_adjoint_vcycle(shape):
     """one V-cycle (and one adjoint V-cycle) built from the marching kernels
