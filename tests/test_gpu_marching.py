@@ -27,6 +27,10 @@ TOL32 = 3e-5
 # of 8 and 6 cells in 16-lane row groups (n_2 = 9 leaves three rows of the last group empty);
 # n_3 = 10, 17 and 18 give ragged x_3 chunks
 SHAPES = [(10, 12, 70), (17, 9, 130)]
+# x_1 remainders at the edge of the row-group case: 76 = 62 + 14 (the largest
+# remainder in 16-lane groups) and 77 = 62 + 15 (one more full segment);
+# n_2 = 10 leaves two rows of the last group empty
+EDGE_SHAPES = [(6, 10, 76), (6, 10, 77)]
 EVEN_SHAPES = [(10, 12, 70), (18, 10, 130)]  # two-level hierarchies
 
 
@@ -55,7 +59,7 @@ def _maxrel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + EDGE_SHAPES)
 @pytest.mark.parametrize("adjoint", [False, True])
 @pytest.mark.parametrize("shifted", [False, True])
 def test_marching_apply_and_residual(shape, adjoint, shifted):
