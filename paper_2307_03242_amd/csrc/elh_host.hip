@@ -1282,8 +1282,15 @@ static int gmres_device(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ
     const bool fn = nrhs * 2 <= FUSE_VALS;
     const int nbn = norm_blocks(len, FUSE_BLOCKS);
     CHK((launch_multidot<CT, CT>(1, r0, 0, len, r0, len, len, nrhs, gpart, fn ? nullptr : gnrm, st)));
-    CHK(launch_gm_start(nrhs, fn ? nullptr : gnrm, fn ? gpart : nullptr, multidot_blocks(1, len, FUSE_BLOCKS), gst, gscale, st));
-    CHK((launch_scale_copy<CT, CT>(gscale, r0, len, V, len, len, nrhs, st)));
+    // with the small reductions, the start and each rotation but the last
+    // run in the scaled copy that follows them, and the last rotation does
+    // the back substitution (one launch each instead of two)
+    if (fn) {
+      CHK(launch_gm_step_copy<T>(nrhs, -1, gpart, multidot_blocks(1, len, FUSE_BLOCKS), gst, gscale, r0, V, len, st));
+    } else {
+      CHK(launch_gm_start(nrhs, gnrm, nullptr, 0, gst, gscale, st));
+      CHK((launch_scale_copy<CT, CT>(gscale, r0, len, V, len, len, nrhs, st)));
+    }
     const int k = (maxit - done) < m ? (maxit - done) : m;
     for (int j = 0; j < k; ++j) {
       CHK(M((const void*)(V + j * vstr), (void*)(Z + j * vstr)));
@@ -1295,10 +1302,15 @@ static int gmres_device(elh_handle* H, KrylovWS& ws, int64_t len, int nrhs, OpAZ
       // Gram-Schmidt update and its norm in one pass
       CHK((launch_axpy_norm<CT, CT>(j + 1, gcoef, V, vstr, len, w, len, nullptr, len, len, nrhs, gpart,
                                     fn ? nullptr : gnrm, st)));
-      CHK(launch_gm_rotate(nrhs, j, fn ? nullptr : gnrm, fn ? gpart : nullptr, nbn, gst, gscale, st));
-      if (j + 1 < k) CHK((launch_scale_copy<CT, CT>(gscale, w, len, V + (j + 1) * vstr, len, len, nrhs, st)));
+      const bool last = j + 1 == k;
+      if (fn && !last) {
+        CHK(launch_gm_step_copy<T>(nrhs, j, gpart, nbn, gst, gscale, w, V + (j + 1) * vstr, len, st));
+      } else {
+        CHK(launch_gm_rotate(nrhs, j, fn ? nullptr : gnrm, fn ? gpart : nullptr, nbn, gst, gscale, st, last ? k : 0,
+                             gcoef));
+        if (!last) CHK((launch_scale_copy<CT, CT>(gscale, w, len, V + (j + 1) * vstr, len, len, nrhs, st)));
+      }
     }
-    CHK(launch_gm_backsolve(nrhs, k, gst, gcoef, st));
     CHK((launch_multiaxpy<CT, CT>(k, gcoef, Z, vstr, len, x, len, len, nrhs, st, done == 0)));
     done += k;
     if (done < maxit) {

@@ -138,9 +138,14 @@ int launch_gm_start(int nrhs, const double* nrm2, const double* part, int nb, do
                     hipStream_t s);
 int launch_gm_hcol(int nrhs, int j, const double* dots, const double* part, int nb, double* st, double* coef,
                    hipStream_t s);
+// bk > 0: also the back substitution over bk columns into coef (the last step)
 int launch_gm_rotate(int nrhs, int j, const double* nrm2, const double* part, int nb, double* st, double* scale,
-                     hipStream_t s);
-int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStream_t s);
+                     hipStream_t s, int bk = 0, double* coef = nullptr);
+// the start (rotation < 0) or rotation j fused with the scaled copy y = x / ||x||
+// that follows it (small-reduction path only: part set, nrhs * 2 <= FUSE_VALS)
+template <typename T>
+int launch_gm_step_copy(int nrhs, int rotation, const double* part, int nb, double* st, double* scale, const void* x,
+                        void* y, int64_t len, hipStream_t s);
 // Outer flexible GMRES bookkeeping on the device (per-rhs record of
 // GO_STRIDE doubles; stat: 4 doubles per rhs: live, jend, residual
 // estimate, non-finite flag).  par: 4 doubles per rhs: active, ||b||, rtol.

@@ -1233,6 +1233,17 @@ __device__ inline zc* gm_sn(double* st, int s) { return gm_g(st, s) + MAXDOT; }
 __device__ inline double* gm_cs(double* st, int s) { return (double*)(gm_sn(st, s) + MAXDOT); }
 
 // start of a restart cycle: beta = ||r||, g = (beta, 0, ...), scale = 1/beta
+// restart start for rhs s: g = ||r0|| e_1, scale = 1/||r0||
+__device__ void gm_start_rhs(int s, const double* __restrict__ nrm2, double* __restrict__ st,
+                             double* __restrict__ scale) {
+  double beta = sqrt(nrm2[2 * s]);
+  zc* g = gm_g(st, s);
+  for (int i = 0; i < MAXDOT; ++i) g[i] = {0.0, 0.0};
+  g[0] = {beta, 0.0};
+  scale[2 * s] = beta > 0 ? 1.0 / beta : 0.0;
+  scale[2 * s + 1] = 0.0;
+}
+
 __global__ void __launch_bounds__(256) k_gm_start(int nrhs, const double* __restrict__ nrm2_in,
                                                    const double* __restrict__ part, int nb,
                                                    double* __restrict__ st, double* __restrict__ scale) {
@@ -1240,12 +1251,7 @@ __global__ void __launch_bounds__(256) k_gm_start(int nrhs, const double* __rest
   const double* __restrict__ nrm2 = small_reduction(nrhs * 2, 2, nrm2_in, part, nb, vals);
   int s = threadIdx.x;
   if (s >= nrhs) return;
-  double beta = sqrt(nrm2[2 * s]);
-  zc* g = gm_g(st, s);
-  for (int i = 0; i < MAXDOT; ++i) g[i] = {0.0, 0.0};
-  g[0] = {beta, 0.0};
-  scale[2 * s] = beta > 0 ? 1.0 / beta : 0.0;
-  scale[2 * s + 1] = 0.0;
+  gm_start_rhs(s, nrm2, st, scale);
 }
 
 // after the dots h_i = <V_i, w>, i <= j: store column j and coef = -h
@@ -1264,15 +1270,10 @@ __global__ void __launch_bounds__(256) k_gm_hcol(int nrhs, int j, const double* 
   }
 }
 
-// after ||w||^2: subdiagonal, previous rotations, new rotation, g update,
-// scale = 1/h_{j+1,j}
-__global__ void __launch_bounds__(256) k_gm_rotate(int nrhs, int j, const double* __restrict__ nrm2_in,
-                                                    const double* __restrict__ part, int nb,
-                                                    double* __restrict__ st, double* __restrict__ scale) {
-  __shared__ double vals[FUSE_VALS];
-  const double* __restrict__ nrm2 = small_reduction(nrhs * 2, 2, nrm2_in, part, nb, vals);
-  int s = threadIdx.x;
-  if (s >= nrhs) return;
+// after ||w||^2, for rhs s: subdiagonal, previous rotations, new rotation,
+// g update, scale = 1/h_{j+1,j}
+__device__ void gm_rotate_rhs(int s, int j, const double* __restrict__ nrm2, double* __restrict__ st,
+                              double* __restrict__ scale) {
   double hn = sqrt(nrm2[2 * s]);
   *gm_H(st, s, j + 1, j) = {hn, 0.0};
   zc* sn = gm_sn(st, s);
@@ -1312,10 +1313,8 @@ __global__ void __launch_bounds__(256) k_gm_rotate(int nrhs, int j, const double
   scale[2 * s + 1] = 0.0;
 }
 
-// y = R^{-1} g over k columns (zero where the triangle is singular)
-__global__ void k_gm_backsolve(int nrhs, int k, const double* __restrict__ st, double* __restrict__ coef) {
-  int s = threadIdx.x;
-  if (s >= nrhs) return;
+// y = R^{-1} g over k columns for rhs s (zero where the triangle is singular)
+__device__ void gm_backsolve_rhs(int s, int k, const double* __restrict__ st, double* __restrict__ coef) {
   double* stw = const_cast<double*>(st);
   const zc* g = gm_g(stw, s);
   zc y[MAXDOT];
@@ -1336,6 +1335,48 @@ __global__ void k_gm_backsolve(int nrhs, int k, const double* __restrict__ st, d
   }
 }
 
+// bk > 0: the last step of a cycle; the back substitution over bk columns
+// follows in the same thread (each rhs's state belongs to one thread)
+__global__ void __launch_bounds__(256) k_gm_rotate(int nrhs, int j, const double* __restrict__ nrm2_in,
+                                                    const double* __restrict__ part, int nb,
+                                                    double* __restrict__ st, double* __restrict__ scale, int bk,
+                                                    double* __restrict__ coef) {
+  __shared__ double vals[FUSE_VALS];
+  const double* __restrict__ nrm2 = small_reduction(nrhs * 2, 2, nrm2_in, part, nb, vals);
+  int s = threadIdx.x;
+  if (s >= nrhs) return;
+  gm_rotate_rhs(s, j, nrm2, st, scale);
+  if (bk > 0) gm_backsolve_rhs(s, bk, st, coef);
+}
+
+// The restart start (rotation < 0) or rotation j of the device GMRES fused
+// with the scaled copy y = x / ||x|| that follows it: every block finishes
+// the small reduction of the norms (same routine and order as the
+// single-block kernels, so the same values), scales its part of x, and
+// block (0, 0) also updates the state.  No block reads what another writes.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gm_step_copy(int nrhs, int rotation, const double* __restrict__ part,
+                                                       int nb, double* __restrict__ st, double* __restrict__ scale,
+                                                       const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                       int64_t len) {
+  __shared__ double vals[FUSE_VALS];
+  const double* __restrict__ nrm2 = small_reduction(nrhs * 2, 2, nullptr, part, nb, vals);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && (int)threadIdx.x < nrhs) {
+    if (rotation < 0) gm_start_rhs(threadIdx.x, nrm2, st, scale);
+    else gm_rotate_rhs(threadIdx.x, rotation, nrm2, st, scale);
+  }
+  const int s = blockIdx.y;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  const double h = sqrt(nrm2[2 * s]);
+  const double ar = h > 0 ? 1.0 / h : 0.0;
+  const cx<T> xv = x[s * len + t];
+  cx<T> out;
+  out.re = (T)(ar * (double)xv.re);
+  out.im = (T)(ar * (double)xv.im);
+  y[s * len + t] = out;
+}
+
 int launch_gm_start(int nrhs, const double* nrm2, const double* part, int nb, double* st, double* scale,
                     hipStream_t s) {
   if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 > FUSE_VALS)) return (int)hipErrorInvalidValue;
@@ -1349,15 +1390,24 @@ int launch_gm_hcol(int nrhs, int j, const double* dots, const double* part, int 
   return (int)hipGetLastError();
 }
 int launch_gm_rotate(int nrhs, int j, const double* nrm2, const double* part, int nb, double* st, double* scale,
-                     hipStream_t s) {
-  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 > FUSE_VALS)) return (int)hipErrorInvalidValue;
-  ELH_LAUNCH(k_gm_rotate, dim3(1), dim3(256), 0, s, nrhs, j, nrm2, part, nb, st, scale);
+                     hipStream_t s, int bk, double* coef) {
+  if (nrhs < 1 || nrhs > MAXRHS_KRYLOV || (part && nrhs * 2 > FUSE_VALS) || (bk > 0 && !coef))
+    return (int)hipErrorInvalidValue;
+  ELH_LAUNCH(k_gm_rotate, dim3(1), dim3(256), 0, s, nrhs, j, nrm2, part, nb, st, scale, bk, coef);
   return (int)hipGetLastError();
 }
-int launch_gm_backsolve(int nrhs, int k, const double* st, double* coef, hipStream_t s) {
-  ELH_LAUNCH(k_gm_backsolve, dim3(1), dim3(64), 0, s, nrhs, k, st, coef);
+template <typename T>
+int launch_gm_step_copy(int nrhs, int rotation, const double* part, int nb, double* st, double* scale, const void* x,
+                        void* y, int64_t len, hipStream_t s) {
+  if (nrhs < 1 || !part || nrhs * 2 > FUSE_VALS) return (int)hipErrorInvalidValue;
+  ELH_LAUNCH((k_gm_step_copy<T>), dim3((unsigned)((len + 255) / 256), nrhs), dim3(256), 0, s, nrhs, rotation,
+             part, nb, st, scale, (const cx<T>*)x, (cx<T>*)y, len);
   return (int)hipGetLastError();
 }
+template int launch_gm_step_copy<double>(int, int, const double*, int, double*, double*, const void*, void*, int64_t,
+                                         hipStream_t);
+template int launch_gm_step_copy<float>(int, int, const double*, int, double*, double*, const void*, void*, int64_t,
+                                        hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Receivers of the FWI misfit: the restriction P_r samples a wavefield at a
